@@ -1,0 +1,305 @@
+"""Oracle, finite-dimensional problems (TEST INFRASTRUCTURE ONLY).
+
+Notation follows the paper (Sec. 2 and Sec. 3):
+
+* dynamics  i d/dt psi = H(u) psi,  H(u) = H0 + sum_c u_c H_c        (Eq. (dir))
+* objective J[u] = Re<psi(T)|psi_f> - alpha/2 int u^2                 (Sec. 2)
+* K steps of length tau = T/K, control u_j constant on step j         (Sec. 3, time grid)
+* step map  psi_{j+1} = exp(-i tau H(u_j)) psi_j  (exact exponential of the
+  piecewise-constant Hamiltonian; the paper's Crank-Nicolson map is not used)
+* discrete objective J_tau = Re<psi_K|psi_f> - tau/2 sum_j alpha_j |u_j|^2
+* adjoint  lambda_K = psi_f, lambda_j = U_j^dagger lambda_{j+1}      (discrete Eq. (adj))
+* gradient g_{j,c} = (1/tau) dJ_tau/du_{j,c}
+           = Im<lambda_j| Hhat_{c,j} |psi_j> - alpha_j u_{j,c}
+  where Hhat_{c,j} = (1/tau) int_0^tau e^{isH_j} H_c e^{-isH_j} ds is the
+  step average of H_c, so that dU_j/du_c = -i tau U_j Hhat_{c,j}.  This is
+  the exact discrete counterpart of Eq. (gradJ); the paper's own discrete
+  formula (Sec. 3, end) is for Crank-Nicolson and is garbled in print.
+* plain method  u <- u + rho g   (Eq. (gradStep), read as ascent since J is
+  maximised)
+* ISM (Algorithm 1, one gradient step per slice): slices s_n = floor(nK/N),
+  t_n = s_n tau, intermediate states
+      phi_n = (T - t_n)/T psi(t_n) + t_n/T chi(t_n)                  (Eq. (cible))
+  slice functional J_n with alpha_n = alpha (t_{n+1}-t_n)/T, beta_n = T/(t_{n+1}-t_n),
+  slice trajectories psi^n from phi_n and chi^n from phi_{n+1}, slice gradient
+  beta_n grad J_n = grad J (Theorem 2), boundaries by propagator assembling
+  M_n = U_{s_{n+1}-1} ... U_{s_n} and 2N matrix-vector products (Sec. 3).
+
+Inner products: states <a|b> = sum conj(a) b; gates <A|B> = Tr(A^dagger B)/d.
+
+Pins (tests/test_oracle_finite.py): closed-form spin rotations, unitarity,
+reversibility, overlap invariance, central finite differences of J_tau,
+scipy's Frechet derivative of expm, ISM == plain gradient iterates, Theorem 1
+(value and argmax by an independent linear solve), Theorem 2 per slice,
+assembled boundaries == sequential propagation, rotor Gauss-Legendre nodes,
+free-rotor phases.  No function here is parity-unpinned.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "slice_starts", "hamiltonian", "step_unitary", "step_unitaries", "hhat",
+    "forward", "backward", "inner", "objective", "gradient", "plain_gradient_method",
+    "assemble", "boundaries", "intermediate_states", "ism_slice_gradient",
+    "ism_gradient", "ism_iterate", "theorem1_functional", "theorem1_argmax",
+]
+
+
+def slice_starts(K: int, N: int) -> np.ndarray:
+    """s_n = floor(n K / N), n = 0..N: a partition 0 = t_0 < ... < t_N = T of the
+    time grid (Sec. 2; the paper allows any partition)."""
+    if not (1 <= N <= K):
+        raise ValueError("need 1 <= N <= K")
+    return np.array([(n * K) // N for n in range(N + 1)], dtype=np.int64)
+
+
+def hamiltonian(H0: np.ndarray, Hc: np.ndarray, uj: np.ndarray) -> np.ndarray:
+    """H(u_j) = H0 + sum_c u_{j,c} H_c  (Eq. (dir) with the control on step j)."""
+    H = np.array(H0, dtype=np.complex128, copy=True)
+    for c in range(Hc.shape[0]):
+        H = H + uj[c] * Hc[c]
+    return H
+
+
+def _eig(H: np.ndarray):
+    Hh = 0.5 * (H + H.conj().T)
+    w, V = np.linalg.eigh(Hh)
+    return w, V
+
+
+def step_unitary(H: np.ndarray, tau: float) -> np.ndarray:
+    """U = exp(-i tau H) for Hermitian H, from its eigendecomposition H = V diag(w) V^dagger."""
+    w, V = _eig(H)
+    return (V * np.exp(-1j * tau * w)[None, :]) @ V.conj().T
+
+
+def step_unitaries(H0, Hc, u, tau):
+    """[U_0, ..., U_{K-1}] for controls u of shape (K, C)."""
+    return [step_unitary(hamiltonian(H0, Hc, u[j]), tau) for j in range(u.shape[0])]
+
+
+def _phi1(x: np.ndarray) -> np.ndarray:
+    """(e^{ix} - 1)/(ix), evaluated as sin(x)/x + i 2 sin^2(x/2)/x, with its series near 0."""
+    out = np.empty(x.shape, dtype=np.complex128)
+    small = np.abs(x) < 1e-4
+    xs = x[small]
+    out[small] = (1 - xs ** 2 / 6 + xs ** 4 / 120) + 1j * (xs / 2 - xs ** 3 / 24)
+    xl = x[~small]
+    out[~small] = np.sin(xl) / xl + 1j * 2 * np.sin(xl / 2) ** 2 / xl
+    return out
+
+
+def hhat(H: np.ndarray, Hcs: np.ndarray, tau: float) -> np.ndarray:
+    """Step-averaged control operators Hhat_c = (1/tau) int_0^tau e^{isH} H_c e^{-isH} ds.
+
+    In the eigenbasis of H: (V^dagger Hhat V)_ab = (V^dagger H_c V)_ab phi1(tau (w_a - w_b)).
+    Returns shape (C, d, d)."""
+    w, V = _eig(H)
+    Phi = _phi1(tau * (w[:, None] - w[None, :]))
+    out = []
+    for c in range(Hcs.shape[0]):
+        A = V.conj().T @ Hcs[c] @ V
+        out.append(V @ (A * Phi) @ V.conj().T)
+    return np.stack(out)
+
+
+def forward(Us, psi0):
+    """psi_0 = psi0, psi_{j+1} = U_j psi_j; returns the list psi_0..psi_K (vectors or matrices)."""
+    out = [np.array(psi0, dtype=np.complex128)]
+    for U in Us:
+        out.append(U @ out[-1])
+    return out
+
+
+def backward(Us, target):
+    """lambda_K = psi_f, lambda_j = U_j^dagger lambda_{j+1}; returns lambda_0..lambda_K."""
+    out = [np.array(target, dtype=np.complex128)]
+    for U in reversed(Us):
+        out.append(U.conj().T @ out[-1])
+    return out[::-1]
+
+
+def inner(a: np.ndarray, b: np.ndarray) -> complex:
+    """<a|b>: sum conj(a) b for states, Tr(a^dagger b)/d for gates (matrices)."""
+    if a.ndim == 1:
+        return complex(np.vdot(a, b))
+    return complex(np.trace(a.conj().T @ b)) / a.shape[0]
+
+
+def objective(psiK, target, u, alpha, tau):
+    """J_tau = Re<psi_K|psi_f> - tau/2 sum_j alpha_j sum_c u_{j,c}^2 and F = |<psi_K|psi_f>|^2."""
+    z = inner(psiK, target)
+    pen = 0.5 * tau * float(np.sum(alpha[:, None] * u ** 2))
+    return z.real - pen, abs(z) ** 2
+
+
+def gradient(H0, Hc, psi0, target, u, T, alpha):
+    """Exact (1/tau) dJ_tau/du of the exponential step map, plus J and F at u.
+
+    Returns (g[K,C], J, F, psi_K)."""
+    K = u.shape[0]
+    tau = T / K
+    Us = step_unitaries(H0, Hc, u, tau)
+    psis = forward(Us, psi0)
+    lams = backward(Us, target)
+    g = np.zeros_like(u)
+    for j in range(K):
+        Hh = hhat(hamiltonian(H0, Hc, u[j]), Hc, tau)
+        for c in range(Hc.shape[0]):
+            g[j, c] = inner(lams[j], Hh[c] @ psis[j]).imag - alpha[j] * u[j, c]
+    J, F = objective(psis[-1], target, u, alpha, tau)
+    return g, J, F, psis[-1]
+
+
+def plain_gradient_method(H0, Hc, psi0, target, u0, T, alpha, rho, iters):
+    """Constant-step gradient ascent u^{k+1} = u^k + rho g(u^k) (Eq. (gradStep)).
+
+    Returns dict with the final u, and per-iteration J^(k), F^(k) (at u^k, before the
+    update) and Err^(k) = tau sum |g^(k)| (the L1 size of the gradient, Algorithm 1 step (e))."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    tau = T / u.shape[0]
+    Js, Fs, Errs = [], [], []
+    for _ in range(iters):
+        g, J, F, _ = gradient(H0, Hc, psi0, target, u, T, alpha)
+        Js.append(J); Fs.append(F); Errs.append(tau * float(np.sum(np.abs(g))))
+        u = u + rho * g
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs)}
+
+
+# ----------------------------------------------------------------------------
+# ISM
+# ----------------------------------------------------------------------------
+
+def assemble(Us, s):
+    """Slice propagators M_n = U_{s_{n+1}-1} ... U_{s_n} (propagator assembling, Sec. 3)."""
+    d = Us[0].shape[0]
+    Ms = []
+    for n in range(len(s) - 1):
+        M = np.eye(d, dtype=np.complex128)
+        for j in range(s[n], s[n + 1]):
+            M = Us[j] @ M
+        Ms.append(M)
+    return Ms
+
+
+def boundaries(Ms, psi0, target):
+    """The 2N products of Sec. 3: Psi_0 = psi0, Psi_{n+1} = M_n Psi_n (forward) and
+    Lambda_N = psi_f, Lambda_n = M_n^dagger Lambda_{n+1} (adjoint).
+    Psi_n = psi(t_n) and Lambda_n = chi(t_n)."""
+    N = len(Ms)
+    Psi = [np.array(psi0, dtype=np.complex128)]
+    for n in range(N):
+        Psi.append(Ms[n] @ Psi[-1])
+    Lam = [None] * (N + 1)
+    Lam[N] = np.array(target, dtype=np.complex128)
+    for n in range(N - 1, -1, -1):
+        Lam[n] = Ms[n].conj().T @ Lam[n + 1]
+    return Psi, Lam
+
+
+def intermediate_states(Psi, Lam, s, K):
+    """phi_n = (T - t_n)/T psi(t_n) + t_n/T chi(t_n)   (Eq. (cible)); t_n/T = s_n/K."""
+    return [(1.0 - s[n] / K) * Psi[n] + (s[n] / K) * Lam[n] for n in range(len(s))]
+
+
+def ism_slice_gradient(Us, Hhats, u, alpha, phi_n, phi_n1, sn, sn1, K):
+    """Gradient of the slice problem n, scaled by beta_n (Theorem 2).
+
+    psi^n from phi_n forward over steps sn..sn1-1 (Eq. (dirpara)); chi^n from phi_{n+1}
+    backward (end condition of the Re-form of J_n, Sec. 2).  Returns
+    beta_n [Im<chi^n_j|Hhat_{c,j}|psi^n_j> - alpha_{n,j} u_{j,c}] for j in [sn, sn1),
+    with alpha_{n,j} = alpha_j / beta_n."""
+    beta = K / (sn1 - sn)
+    psi = [phi_n]
+    for j in range(sn, sn1):
+        psi.append(Us[j] @ psi[-1])
+    chi = [None] * (sn1 - sn + 1)
+    chi[-1] = phi_n1
+    for j in range(sn1 - 1, sn - 1, -1):
+        chi[j - sn] = Us[j].conj().T @ chi[j - sn + 1]
+    C = u.shape[1]
+    g = np.zeros((sn1 - sn, C))
+    for j in range(sn, sn1):
+        for c in range(C):
+            ov = inner(chi[j - sn], Hhats[j][c] @ psi[j - sn]).imag
+            g[j - sn, c] = beta * (ov - (alpha[j] / beta) * u[j, c])
+    return g, psi[-1]
+
+
+def ism_gradient(H0, Hc, psi0, target, u, T, alpha, N):
+    """One ISM gradient evaluation: Algorithm 1 steps (a)-(c) with the boundaries by
+    propagator assembling.  Returns (g[K,C], J, F, phi list, Psi, Lam)."""
+    K = u.shape[0]
+    tau = T / K
+    s = slice_starts(K, N)
+    Us = step_unitaries(H0, Hc, u, tau)
+    Hhats = [hhat(hamiltonian(H0, Hc, u[j]), Hc, tau) for j in range(K)]
+    Ms = assemble(Us, s)
+    Psi, Lam = boundaries(Ms, psi0, target)
+    phi = intermediate_states(Psi, Lam, s, K)
+    g = np.zeros_like(u)
+    for n in range(N):
+        gn, _ = ism_slice_gradient(Us, Hhats, u, alpha, phi[n], phi[n + 1], s[n], s[n + 1], K)
+        g[s[n]:s[n + 1]] = gn
+    J, F = objective(Psi[-1], target, u, alpha, tau)
+    return g, J, F, phi, Psi, Lam
+
+
+def ism_iterate(H0, Hc, psi0, target, u0, T, alpha, rho, iters, N):
+    """ISM (Algorithm 1) with one constant-step gradient step per slice and per iteration.
+
+    Returns the same record as plain_gradient_method."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    tau = T / u.shape[0]
+    Js, Fs, Errs = [], [], []
+    for _ in range(iters):
+        g, J, F, _, _, _ = ism_gradient(H0, Hc, psi0, target, u, T, alpha, N)
+        Js.append(J); Fs.append(F); Errs.append(tau * float(np.sum(np.abs(g))))
+        u = u + rho * g
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs)}
+
+
+# ----------------------------------------------------------------------------
+# Theorem 1
+# ----------------------------------------------------------------------------
+
+def theorem1_functional(Ms, phi, u, alpha, s, K, T):
+    """J_par[u, phi] = sum_n beta_n J_n with J_n in its squared-distance form
+    J_n = -1/2 ||M_n phi_n - phi_{n+1}||^2 - alpha_n/2 tau sum_{j in slice} |u_j|^2 (Sec. 2)."""
+    tau = T / K
+    tot = 0.0
+    for n in range(len(Ms)):
+        beta = K / (s[n + 1] - s[n])
+        diff = Ms[n] @ phi[n] - phi[n + 1]
+        dist2 = float(np.real(np.vdot(diff, diff)))
+        pen = 0.5 * tau * float(np.sum((alpha[s[n]:s[n + 1]] / beta)[:, None] * u[s[n]:s[n + 1]] ** 2))
+        tot += beta * (-0.5 * dist2 - pen)
+    return tot
+
+
+def theorem1_argmax(Ms, psi0, target, s, K):
+    """Maximiser of J_par over the interior phi_1..phi_{N-1} (phi_0 = psi0, phi_N = psi_f
+    fixed), by solving the stationarity conditions as one dense linear system:
+      (beta_{n-1} + beta_n) phi_n - beta_{n-1} M_{n-1} phi_{n-1} - beta_n M_n^dagger phi_{n+1} = 0
+    for n = 1..N-1 (uses M_n^dagger M_n = I).  Independent of Eq. (cible)."""
+    N = len(Ms)
+    d = Ms[0].shape[0]
+    if N == 1:
+        return [np.array(psi0), np.array(target)]
+    beta = [K / (s[n + 1] - s[n]) for n in range(N)]
+    A = np.zeros(((N - 1) * d, (N - 1) * d), dtype=np.complex128)
+    b = np.zeros((N - 1) * d, dtype=np.complex128)
+    for n in range(1, N):
+        r = (n - 1) * d
+        A[r:r + d, r:r + d] = (beta[n - 1] + beta[n]) * np.eye(d)
+        if n - 1 >= 1:
+            A[r:r + d, r - d:r] = -beta[n - 1] * Ms[n - 1]
+        else:
+            b[r:r + d] += beta[n - 1] * Ms[n - 1] @ psi0
+        if n + 1 <= N - 1:
+            A[r:r + d, r + d:r + 2 * d] = -beta[n] * Ms[n].conj().T
+        else:
+            b[r:r + d] += beta[n] * Ms[n].conj().T @ target
+    x = np.linalg.solve(A, b)
+    return [np.array(psi0)] + [x[(n - 1) * d:n * d] for n in range(1, N)] + [np.array(target)]
