@@ -1,0 +1,171 @@
+"""Benchmark: ISM iterations on the rotor batch (molecular-orientation stand-in).
+
+Workload: 256 rigid rotors (j = 0..20, d = 21, H_b = B_b j(j+1) - u cos(theta),
+B_b ~ U(0.8, 1.2)), T = 10, K = 20000 steps, N = 128 slices, psi0 = |0,0>, target =
+top cos(theta) eigenvector in j <= 4, seeded controls u0 = 1 + U(-0.01, 0.01),
+constant step rho = 1.  One benchmark step = one ISM iteration (Algorithm 1 with
+one gradient step per slice): per-step generator data, slice propagator assembly,
+boundary rebuild by 2N products, intermediate states, slice forward/adjoint sweeps
+with the exact gradient, control update.  Inputs are resident in device memory
+before the timed region.
+
+value  = useful propagation steps/s of the FP32 mixed path = B * 2K * steps / time
+         (forward + adjoint, per the metric), with the plain FP64 ISM measured on the
+         same data beside it.
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "propagation steps/s (fwd+adjoint) FP32 vs plain FP64 ISM; p50/p99 solve latency"
+PEAK_ALU = 78.6e12       # non-packed FP32 and FP64 vector FMA rate: 256 CU x 64 lanes x 2 x 2.4 GHz
+
+
+def _sparse_row_costs(prob):
+    """Per-row flop weights of one Taylor term: 4 flops per stored real nonzero (8 if complex)
+    plus 4 for the term scaling and accumulation; returns (H rows sum, per-control rows sum)."""
+    import numpy as np
+    H0 = prob.H0_of(0)
+    pattern = (np.abs(H0) > 0)
+    cplx = np.any(np.abs(H0.imag) > 0)
+    for c in range(prob.C):
+        pattern |= np.abs(prob.Hc[c]) > 0
+        cplx |= np.any(np.abs(prob.Hc[c].imag) > 0)
+    w = 8 if cplx else 4
+    h_rows = float(np.sum(w * pattern.sum(axis=1) + 4))
+    c_rows = [float(np.sum(w * (np.abs(prob.Hc[c]) > 0).sum(axis=1))) for c in range(prob.C)]
+    return h_rows, c_rows
+
+
+def algorithmic_flops(prob, m, S, B):
+    """Algorithmic FP operations per launch of the two hot kernels of the sparse path."""
+    h_rows, c_rows = _sparse_row_costs(prob)
+    K, d, C = prob.K, prob.d, prob.C
+    vec_step = m * S * h_rows                       # one Taylor action on one vector
+    assemble = float(B) * K * d * vec_step          # d basis vectors through every step
+    per_step_slice = (3 * vec_step                  # forward, adjoint, reversal
+                      + C * vec_step                # H applied in each Frechet series
+                      + sum(m * S * cr for cr in c_rows)   # H_c applied to the adjoint terms
+                      + C * 8 * d)                  # overlaps
+    slice_ = float(B) * K * per_step_slice
+    return {"sp_assemble": assemble, "sp_slice": slice_}
+
+
+def run_gpu(prec, prob, steps, warmup, stream_ptr):
+    import torch
+    from paper_1603_01237_amd import _lib
+    h = _lib.from_problem(prob, precision=prec, stream=stream_ptr)
+    h.iterate(warmup, prob.rho, record=False)
+    torch.cuda.synchronize()
+    h.set_timing(True)
+    h.kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.iterate(steps, prob.rho, record=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = h.kernel_times()
+    h.set_timing(False)
+    info = h.info()
+    J, F = h.fidelity()
+    h.close()
+    return {"seconds": t1 - t0, "kernels": kt, "info": info, "J_mean": float(J.mean()),
+            "F_mean": float(F.mean())}
+
+
+def cpu_baseline(prob, n_inst):
+    """The FP64 oracle's ISM iteration (Algorithm 1, one gradient step per slice) on a
+    bounded sample of instances of the same workload, single thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import finite as O
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        for b in range(n_inst):
+            g, J, F, *_ = O.ism_gradient(prob.H0[b], prob.Hc, prob.psi0, prob.target, prob.u0[b],
+                                         prob.T, prob.alpha, prob.N)
+            _ = prob.u0[b] + prob.rho * g
+    dt = time.perf_counter() - t0
+    return {"value": n_inst * 2 * prob.K / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_inst} of {prob.batch} instances x 1 ISM iteration (K={prob.K}, "
+                      f"N={prob.N}), FP64 NumPy, one thread; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=3, help="oracle instances timed (0: skip)")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the multi-GPU sharding of ISM slices and "
+              "instances is a design (see the design notes), not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import problems
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    prob = problems.rotor(batch=args.batch)
+    B = prob.batch
+    res = {"fp32": run_gpu("fp32", prob, args.steps, args.warmup, stream)}
+    if not args.no_fp64:
+        res["fp64"] = run_gpu("fp64", prob, args.steps, args.warmup, stream)
+    useful = B * 2 * prob.K * args.steps
+    r32 = res["fp32"]
+    value = useful / r32["seconds"]
+    # roofline of the dominant kernel of the FP32 path (largest total time)
+    kt = r32["kernels"]
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, tot_ms = kt[dom]
+    flops = algorithmic_flops(prob, r32["info"]["taylor_m"], r32["info"]["taylor_S"], B)
+    achieved = flops.get(dom, 0.0) / (tot_ms / launches * 1e-3) if dom in flops else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"rotor batch: {B} instances, j<=20 (d=21), K={prob.K}, "
+                               f"N={prob.N}, T={prob.T}, one ISM iteration per step",
+                   "precision": "FP32 mixed (FP64 generator data, overlaps, boundaries)"},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
+                     "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU,
+                     "traffic": None},
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
+        "taylor": {"m": r32["info"]["taylor_m"], "S": r32["info"]["taylor_S"]},
+        "final_F_mean": r32["F_mean"],
+    }
+    if "fp64" in res:
+        r64 = res["fp64"]
+        out["fp64_plain"] = {
+            "value": useful / r64["seconds"], "ms_per_step": r64["seconds"] / args.steps * 1e3,
+            "kernels_ms_per_step": {k: v[1] / args.steps for k, v in r64["kernels"].items()},
+            "taylor": {"m": r64["info"]["taylor_m"], "S": r64["info"]["taylor_S"]},
+            "final_F_mean": r64["F_mean"],
+            "fp32_speedup": r64["seconds"] / r32["seconds"],
+            "final_F_abs_diff_vs_fp32": abs(r64["F_mean"] - r32["F_mean"])}
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

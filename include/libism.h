@@ -1,0 +1,211 @@
+/*
+ * libism -- Intermediate State Method (ISM) hot path on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only; no C++ types, no PyTorch types.
+ *
+ * Method (Riahi, Salomon, Glaser, Sugny, "A fully efficient time-parallelized
+ * quantum optimal control algorithm"):
+ *   dynamics   i d/dt psi = H(u) psi,  H(u) = H0 + sum_c u_c H_c        (Sec. 2, Eq. (dir))
+ *   objective  J[u] = Re<psi(T)|psi_f> - alpha/2 int u^2                 (Sec. 2)
+ *   K steps of length tau = T/K, control u_j constant on step j; the step map is
+ *   the exact exponential exp(-i tau H(u_j)) (finite dimension) or Strang
+ *   splitting (Gross-Pitaevskii, Sec. 3 Eq. (OS)).
+ *   ISM (Algorithm 1): N time slices s_n = floor(n K / N); intermediate states
+ *   phi_n = (T - t_n)/T psi(t_n) + t_n/T chi(t_n) (Eq. (cible)); every slice
+ *   runs a forward sweep from phi_n and an adjoint sweep from phi_{n+1}, forms
+ *   beta_n grad J_n = grad J (Theorem 2) and takes one constant-step gradient
+ *   step (Eq. (gradStep), ascent); the boundary states psi(t_n), chi(t_n) are
+ *   rebuilt from assembled slice propagators M_n by 2N matrix-vector products
+ *   (propagator assembling, Sec. 3).  Gross-Pitaevskii uses the BEC variant of
+ *   Sec. 4.C (slice starts on the forward trajectory, slice targets on the
+ *   adjoint trajectory, boundaries by sequential sweeps).
+ *
+ * Conventions for every function below:
+ *   - Complex numbers are interleaved pairs of doubles (re, im), C99
+ *     "double _Complex" compatible; matrices are row-major.
+ *   - The return value is an ism_status.  On error no output argument is written.
+ *     No C++ exception crosses this interface.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently.
+ *   - All device work is issued on the handle's stream in call order.  A call that
+ *     writes a host pointer synchronises that stream before returning; with
+ *     io_device = 1 the pointers are device pointers and the call does not
+ *     synchronise (the result is ready in stream order).
+ *   - The library allocates its own device memory at create time (and for the
+ *     J history of ism_iterate); the caller keeps ownership of every buffer it
+ *     passes in; inputs are copied.
+ */
+#ifndef LIBISM_H
+#define LIBISM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ism_problem ism_problem;
+
+typedef enum ism_status {
+    ISM_OK = 0,
+    ISM_E_ARG = 1,          /* invalid argument: shape, NULL pointer, non-Hermitian H, N > K ... */
+    ISM_E_NOMEM = 2,        /* device or host allocation failed */
+    ISM_E_DEVICE = 3,       /* a HIP runtime call failed */
+    ISM_E_STATE = 4,        /* call order: e.g. a result requested that was never computed */
+    ISM_E_NUMERIC = 5,      /* NaN or Inf in J or in the gradient */
+    ISM_E_UNSUPPORTED = 6,  /* valid request this build does not handle (e.g. d too large) */
+    ISM_E_BUDGET = 7        /* serving: request does not fit the memory budget */
+} ism_status;
+
+typedef enum ism_precision {
+    ISM_FP64 = 0,           /* plain path: every step in FP64 */
+    ISM_FP32_MIXED = 1      /* FP32 complex propagation with FP32 accumulate; per-step
+                               generator data and all overlaps, gradients, boundary states,
+                               J and F formed in FP64 */
+} ism_precision;
+
+typedef enum ism_kind {
+    ISM_STATE = 0,          /* psi0, target are d-vectors; <a|b> = sum conj(a) b */
+    ISM_GATE = 1            /* psi0, target are d x d matrices (evolution operators, Sec. 2
+                               remark); <A|B> = Tr(A^dagger B)/d */
+} ism_kind;
+
+typedef struct ism_options {
+    int precision;          /* ism_precision (default ISM_FP64) */
+    int kind;               /* ism_kind (default ISM_STATE) */
+    int batch;              /* number of independent instances B >= 1 (default 1) */
+    int h0_batched;         /* 1: H0 holds B matrices (B x d x d), 0: one shared H0 (default 0) */
+    const double* alpha;    /* penalty weight: NULL => alpha = 0; else alpha_len doubles */
+    int alpha_len;          /* 1 (constant alpha) or K (alpha_j per step, e.g. a time-dependent
+                               weight as in Sec. 4.B) */
+    int device;             /* HIP device ordinal (default 0) */
+    void* stream;           /* hipStream_t to issue work on; NULL => library-owned stream */
+    int io_device;          /* 1: pointers of set/get_controls, forward, adjoint, gradient,
+                               fidelity and the J history are device pointers (default 0) */
+} ism_options;
+
+/* Fill *opt with the defaults listed above.  opt must not be NULL. */
+void ism_default_options(ism_options* opt);
+
+/*
+ * Create a finite-dimensional problem (Sec. 2 statement of the problem; partition
+ * of Sec. 2; time grid of Sec. 3).
+ *   out     : receives the new handle.
+ *   d       : Hilbert-space dimension, 1 <= d <= 256 for state problems (ISM_STATE),
+ *             d <= 256 for gate problems (ISM_GATE).
+ *   n_ctrl  : number of controls C >= 1.
+ *   H0      : d x d complex (or B x d x d if opt->h0_batched), Hermitian to 1e-12 relative.
+ *   Hc      : C x d x d complex, contiguous, each Hermitian.
+ *   psi0    : initial state: d complex (ISM_STATE) or d x d (ISM_GATE); shared by all instances.
+ *   target  : target psi_f, same shape as psi0.
+ *   T       : final time > 0.
+ *   K       : number of time steps >= 1 (tau = T/K).
+ *   N       : number of ISM slices, 1 <= N <= K.
+ *   opt     : options (NULL => defaults).
+ * The initial controls are zero; set them with ism_set_controls.
+ * Errors: ISM_E_ARG for NULL/invalid sizes/non-Hermitian input, ISM_E_UNSUPPORTED for
+ * sizes outside the limits, ISM_E_NOMEM, ISM_E_DEVICE.
+ */
+int ism_problem_create(ism_problem** out, int d, int n_ctrl, const double* H0, const double* Hc,
+                       const double* psi0, const double* target, double T, int K, int N,
+                       const ism_options* opt);
+
+/*
+ * Create a 1-D Gross-Pitaevskii problem (Sec. 4.C; step map Eq. (OS)):
+ *   i d/dt psi = (-1/2 d_xx + V(x,u) + g |psi|^2) psi,   V(x,u) = V0(x) + u V1(x) + u^2 V2,
+ * on the periodic grid x_m = -L/2 + m L/n_grid, with one scalar control (C = 1).
+ *   n_grid  : 1024 or 4096 (power of two, LDS-resident FFT).
+ *   L       : box length > 0.   g : nonlinearity.
+ *   V0, V1  : n_grid doubles each.   V2 : scalar.
+ *   psi0, target : n_grid complex, normalised with <a|b> = dx sum conj(a) b.
+ *   T, K, N : as above.   opt : precision, batch, device, stream, io_device are used.
+ */
+int ism_problem_create_gpe(ism_problem** out, int n_grid, double L, double g, const double* V0,
+                           const double* V1, double V2, const double* psi0, const double* target,
+                           double T, int K, int N, const ism_options* opt);
+
+/* Free all device memory of the handle (NULL-safe). */
+void ism_problem_destroy(ism_problem* p);
+
+/* Controls u[B][K][C] (FP64), host or device pointer per io_device.  Setting the
+ * controls invalidates the boundary states. */
+int ism_set_controls(ism_problem* p, const double* u);
+int ism_get_controls(ism_problem* p, double* u);
+
+/*
+ * Forward pass at the current controls: per-step propagator data, slice propagators
+ * M_n (propagator assembling), boundary rebuild (2N products) and intermediate states
+ * (Eq. (cible)), J and F.  psi_T (nullable) receives psi(T) per instance:
+ * B x d complex (state), B x d x d (gate) or B x n_grid (GPE).
+ */
+int ism_forward(ism_problem* p, double* psi_T);
+
+/* Adjoint at t = 0 (Eq. (adj) with chi(T) = psi_f): chi_0 (nullable) receives chi(0)
+ * per instance, same shape as psi_T.  Runs ism_forward first if the boundaries are stale. */
+int ism_adjoint(ism_problem* p, double* chi_0);
+
+/*
+ * Gradient g = (1/tau) dJ_tau/du (function-space gradient of Eq. (gradJ), exact for the
+ * discrete step map), computed slice-parallel through Theorem 2:
+ *   g_{j,c} = beta_n [ Im<chi^n_j|Hhat_{c,j}|psi^n_j> - alpha_{n,j} u_{j,c} ],
+ * with Hhat the step average of H_c.  grad receives B x K x C doubles.
+ * ISM_E_NUMERIC if any entry is NaN/Inf.
+ */
+int ism_gradient(ism_problem* p, double* grad);
+
+/*
+ * n_iter ISM iterations (Algorithm 1 with one constant-step gradient step per slice,
+ * u <- u + rho g).  Iteration k records J^(k) (at u^k, before its update) in
+ * J_hist[k*B + b] (nullable; n_iter*B doubles).  An instance whose fidelity
+ * F = |<psi(T)|psi_f>|^2 reaches fid_stop is frozen (pass fid_stop > 1 to disable);
+ * the loop ends early once every instance is frozen.  *iters_done (nullable) receives
+ * the number of iterations the loop ran.  ISM_E_NUMERIC if J becomes NaN/Inf.
+ */
+int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double* J_hist,
+                int* iters_done);
+
+/* J = Re<psi(T)|psi_f> - tau/2 sum_j alpha_j |u_j|^2 and F = |<psi(T)|psi_f>|^2 per instance
+ * (gate: Re Tr(W^+ U)/d and |Tr(W^+ U)|^2/d^2), B doubles each (either may be NULL).
+ * Recomputes the boundaries if the controls changed since the last forward pass. */
+int ism_fidelity(ism_problem* p, double* J, double* F);
+
+/* Read-only description of a handle. */
+typedef struct ism_info {
+    int path;           /* 0 sparse state path, 1 dense gate path (MFMA), 2 GPE split-step */
+    int d, n_ctrl, K, N, batch, precision, kind;
+    int ell_width;      /* sparse path: stored nonzeros per row of H */
+    size_t device_bytes;/* device memory held by the handle */
+    int taylor_m;       /* sparse path: largest Taylor term count over instances at the last
+                           forward pass (0 if none yet; reading it synchronises the stream) */
+    int taylor_S;       /* sparse path: largest sub-step count, same convention */
+} ism_info;
+int ism_problem_info(const ism_problem* p, ism_info* info);
+
+/*
+ * Per-kernel timing (tracing).  With timing enabled, every kernel launch of the handle is
+ * bracketed by two HIP events recorded on the handle's stream.  ism_kernel_times
+ * synchronises the stream, sums the event intervals per kernel name into
+ * out[0..*n_entries) (at most max_entries; names are static strings) and clears the
+ * record.  Timing adds two event records per launch and no synchronisation.
+ */
+typedef struct ism_kernel_time {
+    const char* name;
+    int launches;
+    double total_ms;
+} ism_kernel_time;
+int ism_set_timing(ism_problem* p, int enable);
+int ism_kernel_times(ism_problem* p, ism_kernel_time* out, int max_entries, int* n_entries);
+
+/* Human-readable name of a status code (static storage). */
+const char* ism_status_string(int status);
+
+/* Device memory (bytes) a problem of this shape would hold; used for admission by
+ * memory budget.  kind/precision as in ism_options; path chosen as ism_problem_create
+ * would.  Returns 0 on invalid input. */
+size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kind, int precision,
+                             int gpe_grid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBISM_H */

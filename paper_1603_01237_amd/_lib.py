@@ -1,0 +1,316 @@
+"""ctypes binding of libism (argument marshalling only; every step runs in the HIP library).
+
+The library must be built (``python -m paper_1603_01237_amd.build``); importing this
+module raises if ``libism.so`` is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libism.so")
+
+ISM_OK, ISM_E_ARG, ISM_E_NOMEM, ISM_E_DEVICE, ISM_E_STATE, ISM_E_NUMERIC, ISM_E_UNSUPPORTED, ISM_E_BUDGET = range(8)
+FP64, FP32_MIXED = 0, 1
+STATE, GATE = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
+
+EXPORTED = [
+    "ism_default_options", "ism_problem_create", "ism_problem_create_gpe", "ism_problem_destroy",
+    "ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient",
+    "ism_iterate", "ism_fidelity", "ism_problem_info", "ism_status_string", "ism_problem_footprint",
+    "ism_set_timing", "ism_kernel_times",
+]
+
+
+class IsmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} (status {code})")
+        self.code = code
+
+
+class Options(ct.Structure):
+    _fields_ = [("precision", ct.c_int), ("kind", ct.c_int), ("batch", ct.c_int),
+                ("h0_batched", ct.c_int), ("alpha", ct.POINTER(ct.c_double)),
+                ("alpha_len", ct.c_int), ("device", ct.c_int), ("stream", ct.c_void_p),
+                ("io_device", ct.c_int)]
+
+
+class Info(ct.Structure):
+    _fields_ = [("path", ct.c_int), ("d", ct.c_int), ("n_ctrl", ct.c_int), ("K", ct.c_int),
+                ("N", ct.c_int), ("batch", ct.c_int), ("precision", ct.c_int), ("kind", ct.c_int),
+                ("ell_width", ct.c_int), ("device_bytes", ct.c_size_t), ("taylor_m", ct.c_int),
+                ("taylor_S", ct.c_int)]
+
+
+class KernelTime(ct.Structure):
+    _fields_ = [("name", ct.c_char_p), ("launches", ct.c_int), ("total_ms", ct.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libism.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run python -m paper_1603_01237_amd.build")
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).  Loading
+    # torch first makes libism bind to that runtime, so one process never holds two HIP
+    # runtimes (device memory and streams from torch then work with libism handles).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ct.CDLL(LIB_PATH)
+    dp = ct.POINTER(ct.c_double)
+    vp = ct.c_void_p
+    L.ism_default_options.argtypes = [ct.POINTER(Options)]
+    L.ism_default_options.restype = None
+    L.ism_problem_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.c_int, vp, vp, vp, vp,
+                                     ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Options)]
+    L.ism_problem_create_gpe.argtypes = [ct.POINTER(vp), ct.c_int, ct.c_double, ct.c_double, vp,
+                                         vp, ct.c_double, vp, vp, ct.c_double, ct.c_int, ct.c_int,
+                                         ct.POINTER(Options)]
+    L.ism_problem_destroy.argtypes = [vp]
+    L.ism_problem_destroy.restype = None
+    for name in ("ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint",
+                 "ism_gradient"):
+        getattr(L, name).argtypes = [vp, vp]
+    L.ism_iterate.argtypes = [vp, ct.c_int, ct.c_double, ct.c_double, vp, ct.POINTER(ct.c_int)]
+    L.ism_fidelity.argtypes = [vp, vp, vp]
+    L.ism_problem_info.argtypes = [vp, ct.POINTER(Info)]
+    L.ism_status_string.argtypes = [ct.c_int]
+    L.ism_status_string.restype = ct.c_char_p
+    L.ism_set_timing.argtypes = [vp, ct.c_int]
+    L.ism_set_timing.restype = ct.c_int
+    L.ism_kernel_times.argtypes = [vp, ct.POINTER(KernelTime), ct.c_int, ct.POINTER(ct.c_int)]
+    L.ism_kernel_times.restype = ct.c_int
+    L.ism_problem_footprint.argtypes = [ct.c_int] * 7 + [ct.c_int]
+    L.ism_problem_footprint.restype = ct.c_size_t
+    for name in ("ism_problem_create", "ism_problem_create_gpe", "ism_set_controls",
+                 "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient", "ism_iterate",
+                 "ism_fidelity", "ism_problem_info"):
+        getattr(L, name).restype = ct.c_int
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    return lib().ism_status_string(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != ISM_OK:
+        raise IsmError(code, what)
+
+
+def _cptr(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def _as_c128(x, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def footprint(d, n_ctrl, K, N, batch=1, kind=STATE, precision=FP64, gpe_grid=0) -> int:
+    return int(lib().ism_problem_footprint(d, n_ctrl, K, N, batch, kind, precision, gpe_grid))
+
+
+class Problem:
+    """One libism handle.  Host I/O uses NumPy arrays; with ``io_device=True`` the
+    controls, gradients and states are exchanged as device tensors (torch.cuda),
+    passed by pointer."""
+
+    def __init__(self, handle, shape_state, d, C, K, N, B, io_device, gpe_n=0):
+        self._h = handle
+        self.state_shape = shape_state
+        self.d, self.C, self.K, self.N, self.B = d, C, K, N, B
+        self.io_device = io_device
+        self.gpe_n = gpe_n
+
+    # ------------------------------------------------------------------ creation
+    @classmethod
+    def create(cls, H0, Hc, psi0, target, T, K, N, precision="fp64", kind="state", batch=1,
+               h0_batched=False, alpha=None, device=0, stream=None, io_device=False):
+        L = lib()
+        Hc = _as_c128(Hc)
+        C, d = Hc.shape[0], Hc.shape[-1]
+        H0 = _as_c128(H0)
+        if h0_batched and H0.shape != (batch, d, d):
+            raise ValueError("batched H0 must have shape (batch, d, d)")
+        kind_i = GATE if kind == "gate" else STATE
+        sshape = (d, d) if kind_i == GATE else (d,)
+        psi0 = _as_c128(psi0, sshape)
+        target = _as_c128(target, sshape)
+        o = Options()
+        L.ism_default_options(ct.byref(o))
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.kind = kind_i
+        o.batch = int(batch)
+        o.h0_batched = 1 if h0_batched else 0
+        al = None
+        if alpha is not None:
+            al = np.ascontiguousarray(np.atleast_1d(np.asarray(alpha, dtype=np.float64)))
+            o.alpha = al.ctypes.data_as(ct.POINTER(ct.c_double))
+            o.alpha_len = al.shape[0]
+        o.device = int(device)
+        o.stream = stream
+        o.io_device = 1 if io_device else 0
+        h = ct.c_void_p()
+        _check(L.ism_problem_create(ct.byref(h), d, C, _cptr(H0), _cptr(Hc), _cptr(psi0),
+                                    _cptr(target), float(T), int(K), int(N), ct.byref(o)),
+               "ism_problem_create")
+        return cls(h, sshape, d, C, int(K), int(N), int(batch), io_device)
+
+    @classmethod
+    def create_gpe(cls, n, L_box, g, V0, V1, V2, psi0, target, T, K, N, precision="fp64",
+                   batch=1, device=0, stream=None, io_device=False):
+        L = lib()
+        V0 = np.ascontiguousarray(np.asarray(V0, dtype=np.float64))
+        V1 = np.ascontiguousarray(np.asarray(V1, dtype=np.float64))
+        psi0 = _as_c128(psi0, (n,))
+        target = _as_c128(target, (n,))
+        o = Options()
+        L.ism_default_options(ct.byref(o))
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.batch = int(batch)
+        o.device = int(device)
+        o.stream = stream
+        o.io_device = 1 if io_device else 0
+        h = ct.c_void_p()
+        _check(L.ism_problem_create_gpe(ct.byref(h), int(n), float(L_box), float(g), _cptr(V0),
+                                        _cptr(V1), float(V2), _cptr(psi0), _cptr(target),
+                                        float(T), int(K), int(N), ct.byref(o)),
+               "ism_problem_create_gpe")
+        return cls(h, (n,), n, 1, int(K), int(N), int(batch), io_device, gpe_n=n)
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if self._h:
+            lib().ism_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ------------------------------------------------------------------ helpers
+    def _out(self, shape, dtype):
+        if self.io_device:
+            import torch
+            tdt = torch.float64 if dtype == np.float64 else torch.complex128
+            return torch.empty(shape, dtype=tdt, device="cuda")
+        return np.empty(shape, dtype=dtype)
+
+    @staticmethod
+    def _ptr(a):
+        if hasattr(a, "data_ptr"):
+            return ct.c_void_p(a.data_ptr())
+        return _cptr(a)
+
+    # ------------------------------------------------------------------ API
+    def set_controls(self, u):
+        if self.io_device:
+            if tuple(u.shape) != (self.B, self.K, self.C) or not u.is_contiguous():
+                raise ValueError("controls must be a contiguous (B, K, C) float64 device tensor")
+            _check(lib().ism_set_controls(self._h, self._ptr(u)), "ism_set_controls")
+            return
+        a = np.ascontiguousarray(np.asarray(u, dtype=np.float64)).reshape(self.B, self.K, self.C)
+        _check(lib().ism_set_controls(self._h, _cptr(a)), "ism_set_controls")
+
+    def get_controls(self):
+        out = self._out((self.B, self.K, self.C), np.float64)
+        _check(lib().ism_get_controls(self._h, self._ptr(out)), "ism_get_controls")
+        return out
+
+    def forward(self, want_state=True):
+        out = self._out((self.B,) + self.state_shape, np.complex128) if want_state else None
+        _check(lib().ism_forward(self._h, self._ptr(out) if out is not None else None), "ism_forward")
+        return out
+
+    def adjoint(self, want_state=True):
+        out = self._out((self.B,) + self.state_shape, np.complex128) if want_state else None
+        _check(lib().ism_adjoint(self._h, self._ptr(out) if out is not None else None), "ism_adjoint")
+        return out
+
+    def gradient(self):
+        out = self._out((self.B, self.K, self.C), np.float64)
+        _check(lib().ism_gradient(self._h, self._ptr(out)), "ism_gradient")
+        return out
+
+    def iterate(self, n_iter, rho, fid_stop=2.0, record=True):
+        Jh = self._out((max(n_iter, 1), self.B), np.float64) if record else None
+        done = ct.c_int(0)
+        _check(lib().ism_iterate(self._h, int(n_iter), float(rho), float(fid_stop),
+                                 self._ptr(Jh) if Jh is not None else None, ct.byref(done)),
+               "ism_iterate")
+        if Jh is not None:
+            Jh = Jh[:n_iter]
+        return Jh, done.value
+
+    def fidelity(self):
+        J = self._out((self.B,), np.float64)
+        F = self._out((self.B,), np.float64)
+        _check(lib().ism_fidelity(self._h, self._ptr(J), self._ptr(F)), "ism_fidelity")
+        return J, F
+
+    def set_timing(self, enable=True):
+        _check(lib().ism_set_timing(self._h, 1 if enable else 0), "ism_set_timing")
+
+    def kernel_times(self) -> dict:
+        """{kernel name: (launches, total ms)} since the last call (synchronises)."""
+        arr = (KernelTime * 32)()
+        n = ct.c_int(0)
+        _check(lib().ism_kernel_times(self._h, arr, 32, ct.byref(n)), "ism_kernel_times")
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+    def info(self) -> dict:
+        i = Info()
+        _check(lib().ism_problem_info(self._h, ct.byref(i)), "ism_problem_info")
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+
+def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=None,
+                 io_device=False, set_u=True):
+    """Create a handle from a ``problems.FiniteProblem`` (or ``problems.GpeProblem``)."""
+    if hasattr(prob, "V0"):
+        B = prob.batch if batch is None else batch
+        p = Problem.create_gpe(prob.n, prob.L, prob.g, prob.V0, prob.V1, prob.V2, prob.psi0,
+                               prob.target, prob.T, prob.K, prob.N if N is None else N,
+                               precision=precision, batch=B, device=device, stream=stream,
+                               io_device=io_device)
+        if set_u:
+            p.set_controls(prob.u0[:B])
+        return p
+    B = prob.batch if batch is None else batch
+    H0 = prob.H0[:B] if prob.H0.ndim == 3 else prob.H0
+    al = prob.alpha if np.any(prob.alpha != 0) else None
+    p = Problem.create(H0, prob.Hc, prob.psi0, prob.target, prob.T, prob.K,
+                       prob.N if N is None else N, precision=precision, kind=prob.kind, batch=B,
+                       h0_batched=prob.H0.ndim == 3, alpha=al, device=device, stream=stream,
+                       io_device=io_device)
+    if set_u:
+        p.set_controls(prob.u0[:B])
+    return p

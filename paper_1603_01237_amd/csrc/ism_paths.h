@@ -1,0 +1,34 @@
+// Per-path entry points used by the host runtime (ism_api.cpp).
+#pragma once
+
+#include "ism_internal.h"
+
+namespace ism {
+
+// shared host helpers (ism_api.cpp)
+int dev_alloc(ism_problem* p, void** ptr, size_t bytes);
+int dev_upload(ism_problem* p, void** ptr, const void* host, size_t bytes);
+int copy_out(ism_problem* p, void* dst, const void* src, size_t bytes);
+int copy_rows_out(ism_problem* p, void* dst, const void* src, size_t row_bytes, size_t src_pitch,
+                  int rows);
+int read_flags(ism_problem* p, int* host_flags);
+int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism_options* o);
+int validate_common(int d, int C, double T, int K, int N, const ism_options* o);
+
+// dense gate path (k_gate.hip)
+int gate_create(ism_problem* p, const double* H0, int h0_batched, const double* Hc,
+                const double* psi0, const double* target);
+int gate_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active);
+int gate_slice_pass(ism_problem* p, int update, double rho, double* grad, bool use_active);
+int gate_copy_state(ism_problem* p, double* out, int which_end);
+size_t gate_footprint_extra(int d, int C, int K, int N, int batch, int precision);
+
+// Gross-Pitaevskii path (k_gpe.hip)
+int gpe_create(ism_problem* p, int n_grid, double L, double g, const double* V0, const double* V1,
+               double V2, const double* psi0, const double* target);
+int gpe_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active);
+int gpe_slice_pass(ism_problem* p, int update, double rho, double* grad, bool use_active);
+int gpe_copy_state(ism_problem* p, double* out, int which_end);
+size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision);
+
+}  // namespace ism

@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol of
+include/libism.h, and rejects invalid arguments before touching the device."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+import problems
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    with open(os.path.join(ROOT, "include", "libism.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ism_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1603_01237_amd import _lib
+    L = _lib.lib()
+    syms = _header_symbols()
+    assert "ism_problem_create" in syms and "ism_iterate" in syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(_lib.EXPORTED)
+
+
+def test_status_strings():
+    from paper_1603_01237_amd import _lib
+    for code in range(8):
+        assert _lib.status_string(code)
+    assert _lib.status_string(99) == "unknown status"
+
+
+def _create(**kw):
+    from paper_1603_01237_amd import _lib
+    p = problems.spin2(K=10, N=2)
+    args = dict(H0=p.H0, Hc=p.Hc, psi0=p.psi0, target=p.target, T=1.0, K=10, N=2)
+    args.update(kw)
+    return _lib.Problem.create(**args)
+
+
+@pytest.mark.parametrize("kw", [
+    {"N": 11},                 # N > K
+    {"N": 0},
+    {"K": 0, "N": 0},
+    {"T": -1.0},
+    {"T": float("nan")},
+    {"batch": 0},
+])
+def test_invalid_sizes_rejected(kw):
+    from paper_1603_01237_amd import _lib
+    with pytest.raises(_lib.IsmError) as e:
+        _create(**kw)
+    assert e.value.code == _lib.ISM_E_ARG
+
+
+def test_non_hermitian_rejected():
+    from paper_1603_01237_amd import _lib
+    p = problems.spin2()
+    H = p.H0.copy()
+    H[0, 1] = 1.0
+    with pytest.raises(_lib.IsmError) as e:
+        _create(H0=H)
+    assert e.value.code == _lib.ISM_E_ARG
+    Hc = p.Hc.copy()
+    Hc[1, 0, 1] = 0.3j          # sigma_y entry no longer conjugate-symmetric
+    with pytest.raises(_lib.IsmError) as e:
+        _create(Hc=Hc)
+    assert e.value.code == _lib.ISM_E_ARG
+
+
+def test_nan_inputs_rejected():
+    from paper_1603_01237_amd import _lib
+    p = problems.spin2()
+    psi = p.psi0.copy()
+    psi[1] = np.nan
+    with pytest.raises(_lib.IsmError) as e:
+        _create(psi0=psi)
+    assert e.value.code == _lib.ISM_E_ARG
+    with pytest.raises(_lib.IsmError) as e:
+        _create(alpha=np.array([np.inf]))
+    assert e.value.code == _lib.ISM_E_ARG
+    with pytest.raises(_lib.IsmError) as e:
+        _create(alpha=np.ones(3))      # alpha_len neither 1 nor K
+    assert e.value.code == _lib.ISM_E_ARG
+
+
+def test_null_pointers_rejected():
+    from paper_1603_01237_amd import _lib
+    L = _lib.lib()
+    h = ct.c_void_p()
+    o = _lib.Options()
+    L.ism_default_options(ct.byref(o))
+    assert L.ism_problem_create(ct.byref(h), 4, 1, None, None, None, None, 1.0, 4, 2, ct.byref(o)) == _lib.ISM_E_ARG
+    assert L.ism_forward(None, None) == _lib.ISM_E_ARG
+    assert L.ism_gradient(None, None) == _lib.ISM_E_ARG
+    assert L.ism_iterate(None, 1, 0.1, 2.0, None, None) == _lib.ISM_E_ARG
+    assert L.ism_fidelity(None, None, None) == _lib.ISM_E_ARG
+    assert L.ism_set_controls(None, None) == _lib.ISM_E_ARG
+    L.ism_problem_destroy(None)
+
+
+def test_footprint_scales():
+    from paper_1603_01237_amd import _lib
+    a = _lib.footprint(21, 1, 20000, 128, 256)
+    b = _lib.footprint(21, 1, 20000, 128, 128)
+    assert a > b > 0
+    assert _lib.footprint(21, 1, 100, 200, 1) == 0      # N > K
+    assert _lib.footprint(256, 16, 2000, 64, 1, kind=_lib.GATE) > 0

@@ -1,0 +1,207 @@
+"""GPU parity of the sparse state path (path (b)) against the FP64 oracle, through the C ABI.
+
+Tolerances (per instance, norms over the whole output):
+  FP64 path      : relative L2 <= tol64(K) = max(1e-12, 2e-14 sqrt(K)) on psi(T), g, J, u
+                   (1e-10 on u after 50 iterations).  Two independent FP64 evaluations of the
+                   exponential step map (eigendecomposition vs Pade scaling-and-squaring) of the
+                   stiff rotor generator (||H|| ~ 500, ||tau H|| ~ 0.25) already differ by
+                   ~1.5e-13 after 4000 steps, growing like sqrt(K): rounding of unitary steps
+                   adds up as a random walk.  tol64 is 1e-12 for K <= 2500.
+  FP32 mixed path: ||psi_gpu(T) - psi_ref(T)||_2 <= 1e-4, ||g_gpu - g_ref|| / ||g_ref|| <= 1e-3
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import problems
+from oracle import finite as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    from paper_1603_01237_amd import _lib
+    return _lib
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def tol64(K):
+    return max(1e-12, 2e-14 * np.sqrt(K))
+
+
+def _oracle_grad(p, b, u):
+    return O.gradient(p.H0_of(b), p.Hc, p.psi0, p.target, u, p.T, p.alpha)
+
+
+CASES = [
+    ("spin2_K40_N3", lambda: problems.spin2(K=40, N=3)),
+    ("spin2_K37_N5_ragged", lambda: problems.spin2(K=37, N=5)),
+    ("spin2_K16_N16_NeqK", lambda: problems.spin2(K=16, N=16)),
+    ("spin2_K25_N1", lambda: problems.spin2(K=25, N=1)),
+    ("rotor_B3_K90_N7", lambda: problems.rotor(batch=3, K=90, N=7, T=0.5)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_fp64_forward_gradient_parity(name, mk):
+    _say("case", name, "fp64")
+    P = _P()
+    p = mk()
+    with P.from_problem(p, precision="fp64") as h:
+        psiT = h.forward()
+        chi0 = h.adjoint()
+        J, F = h.fidelity()
+        g = h.gradient()
+    for b in range(p.batch):
+        gr, Jr, Fr, psiK = _oracle_grad(p, b, p.u0[b])
+        lam0 = O.backward(O.step_unitaries(p.H0_of(b), p.Hc, p.u0[b], p.T / p.K), p.target)[0]
+        assert _rel(psiT[b], psiK) <= 1e-12
+        assert _rel(chi0[b], lam0) <= 1e-12
+        assert abs(J[b] - Jr) <= 1e-12 and abs(F[b] - Fr) <= 1e-12
+        assert _rel(g[b], gr) <= 1e-12, _rel(g[b], gr)
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_fp32_mixed_parity(name, mk):
+    _say("case", name, "fp32")
+    P = _P()
+    p = mk()
+    with P.from_problem(p, precision="fp32") as h:
+        psiT = h.forward()
+        J, F = h.fidelity()
+        g = h.gradient()
+    for b in range(p.batch):
+        gr, Jr, Fr, psiK = _oracle_grad(p, b, p.u0[b])
+        assert np.linalg.norm(psiT[b] - psiK) <= 1e-4
+        assert abs(F[b] - Fr) <= 1e-4
+        assert _rel(g[b], gr) <= 1e-3, _rel(g[b], gr)
+
+
+def test_alpha_time_dependent_fp64():
+    _say("case alpha")
+    P = _P()
+    p = problems.spin2(K=30, N=4)
+    al = 0.3 + 0.2 * np.cos(np.arange(30))          # alpha_j per step
+    with P.Problem.create(p.H0, p.Hc, p.psi0, p.target, p.T, p.K, p.N, alpha=al) as h:
+        h.set_controls(p.u0)
+        g = h.gradient()
+        J, F = h.fidelity()
+    gr, Jr, Fr, _ = O.gradient(p.H0, p.Hc, p.psi0, p.target, p.u0[0], p.T, al)
+    assert _rel(g[0], gr) <= 1e-12
+    assert abs(J[0] - Jr) <= 1e-12
+
+
+def test_cfg0_iterate_equals_plain_gradient_fp64():
+    """Two coupled spins, K=1000, N=8, 50 iterations, step 0.5 (the small configuration):
+    the ISM iterates equal the plain gradient method's (Theorem 2)."""
+    _say("case cfg0 iterate")
+    P = _P()
+    p = problems.spin2()
+    ref = O.plain_gradient_method(p.H0, p.Hc, p.psi0, p.target, p.u0[0], p.T, p.alpha, p.rho, 50)
+    with P.from_problem(p, precision="fp64") as h:
+        Jh, done = h.iterate(50, p.rho)
+        u = h.get_controls()
+        J, F = h.fidelity()
+    assert done == 50
+    assert np.max(np.abs(Jh[:, 0] - ref["J"])) <= 1e-10
+    assert _rel(u[0], ref["u"]) <= 1e-10
+    gr, Jr, Fr, _ = _oracle_grad(p, 0, ref["u"])
+    assert abs(F[0] - Fr) <= 1e-10
+
+
+def test_cfg0_iterate_fp32_final_fidelity():
+    _say("case cfg0 iterate fp32")
+    P = _P()
+    p = problems.spin2()
+    ref = O.plain_gradient_method(p.H0, p.Hc, p.psi0, p.target, p.u0[0], p.T, p.alpha, p.rho, 50)
+    Fref = O.gradient(p.H0, p.Hc, p.psi0, p.target, ref["u"], p.T, p.alpha)[2]
+    with P.from_problem(p, precision="fp32") as h:
+        h.iterate(50, p.rho)
+        J, F = h.fidelity()
+    assert abs(F[0] - Fref) <= 1e-4
+
+
+def test_fid_stop_freezes_instances():
+    _say("case fid_stop")
+    P = _P()
+    p = problems.spin2(K=100, N=4)
+    with P.from_problem(p) as h:
+        Jh, done = h.iterate(200, 0.5, fid_stop=0.9)
+        J, F = h.fidelity()
+        u1 = h.get_controls()
+        Jh2, done2 = h.iterate(5, 0.5, fid_stop=0.9)
+        u2 = h.get_controls()
+    assert 0 < done < 200
+    assert F[0] >= 0.9
+    assert done2 == 0 and np.array_equal(u1, u2)
+
+
+def test_numeric_error_reported_for_nan_controls():
+    _say("case nan")
+    import torch
+    P = _P()
+    p = problems.spin2(K=20, N=2)
+    u = torch.tensor(p.u0, dtype=torch.float64, device="cuda").contiguous()
+    u[0, 3, 1] = float("nan")
+    with P.from_problem(p, io_device=True, set_u=False) as h:
+        h.set_controls(u)
+        with pytest.raises(P.IsmError) as e:
+            h.gradient()
+        assert e.value.code == P.ISM_E_NUMERIC
+        with pytest.raises(P.IsmError) as e:
+            h.iterate(2, 0.1)
+        assert e.value.code == P.ISM_E_NUMERIC
+
+
+def test_device_io_matches_host_io():
+    _say("case device io")
+    import torch
+    P = _P()
+    p = problems.rotor(batch=2, K=50, N=5, T=0.4)
+    with P.from_problem(p) as h:
+        g_host = h.gradient()
+        psi_host = h.forward()
+    with P.from_problem(p, io_device=True, set_u=False) as h:
+        h.set_controls(torch.tensor(p.u0, dtype=torch.float64, device="cuda"))
+        g_dev = h.gradient()
+        psi_dev = h.forward()
+        torch.cuda.synchronize()
+    assert np.array_equal(g_dev.cpu().numpy(), g_host)
+    assert np.array_equal(psi_dev.cpu().numpy(), psi_host)
+
+
+def test_rotor_full_size_sampled():
+    """The benchmark's launch configuration (256 rotors, K=20000, N=128), FP32 mixed and
+    FP64; two instances are checked against the oracle one by one."""
+    _say("case rotor full size")
+    P = _P()
+    p = problems.rotor()
+    res = {}
+    for prec in ("fp32", "fp64"):
+        with P.from_problem(p, precision=prec) as h:
+            g = h.gradient()
+            psiT = h.forward()
+        res[prec] = (g, psiT)
+    for b in (0, 255):
+        gr, Jr, Fr, psiK = _oracle_grad(p, b, p.u0[b])
+        g64, psi64 = res["fp64"][0][b], res["fp64"][1][b]
+        g32, psi32 = res["fp32"][0][b], res["fp32"][1][b]
+        _say("instance", b, "fp64 g", _rel(g64, gr), "psi", _rel(psi64, psiK),
+             "fp32 g", _rel(g32, gr), "psi", np.linalg.norm(psi32 - psiK))
+        assert _rel(psi64, psiK) <= tol64(p.K)
+        assert _rel(g64, gr) <= tol64(p.K)
+        assert np.linalg.norm(psi32 - psiK) <= 1e-4
+        assert _rel(g32, gr) <= 1e-3
+    # every instance: unit norm of psi(T) and finite gradients
+    for prec in ("fp32", "fp64"):
+        assert np.all(np.abs(np.linalg.norm(res[prec][1], axis=1) - 1) <= 1e-5)
+        assert np.all(np.isfinite(res[prec][0]))
