@@ -1,12 +1,588 @@
-// Dense gate path (evolution operators): placeholder until the MFMA kernels land.
+// Dense gate path (evolution operators, the remark of Sec. 2): the propagated object
+// is the d x d evolution operator, psi0 = I, target W, <A|B> = Tr(A^+ B)/d.
+//
+// One ISM iteration (Algorithm 1, one gradient step per slice):
+//   build     U_j = exp(-i tau H_j) for every step, in FP64 (row r of U_j is the
+//             action of exp(-i tau conj(H_j)) on e_r, a truncated Taylor series of a
+//             sparse generator), stored in the path's precision, re/im planes split;
+//   assemble  P_j = U_j U_{j-1} ... U_{s_n} for every step of slice n (chain of batched
+//             complex GEMMs over the slices); M_n = P_{s_{n+1}-1}  (propagator
+//             assembling, Sec. 3);
+//   boundary  Psi_{n+1} = M_n Psi_n, Lambda_n = M_n^+ Lambda_{n+1} (FP64 GEMMs),
+//             phi_n (Eq. (cible)), J and F;
+//   sweeps    the slice trajectories from phi_n (forward) and phi_{n+1} (adjoint) are
+//             X_j = P_{j-1} phi_n and Y_j = P_{j-1} (M_n^+ phi_{n+1}), one batched GEMM
+//             [X_j | Y_j] = P_{j-1} [phi_n | M_n^+ phi_{n+1}] over every step at once;
+//   gradient  g_{j,c} = beta_n Im Tr(Y_j^+ Hhat_{c,j} X_j)/d - alpha_j u_{j,c} (Theorem 2),
+//             with the step average Hhat of H_c evaluated column by column through
+//               <y|Hhat_c|x> = sum_{a+b<=m} w_ab <(tau H')^a y | H_c | (tau H')^b x>,
+//               w_ab = i^{a+b} (-1)^b / ((a+b+1) a! b!),  H' = H_j - s,
+//             which is the series of (1/tau) int_0^tau e^{isH} H_c e^{-isH} ds written with
+//             Krylov vectors of the two states (no extra dense product);
+//   update    u += rho g (Eq. (gradStep), ascent).
+//
+// Complex GEMM: C = op(A) op(B), op in {N, conjugate transpose}, on MFMA
+// (v_mfma_*_16x16x4) with the real and imaginary tiles staged separately in LDS;
+// 64 x 64 output tile per workgroup of four wavefronts, 32 x 32 per wavefront,
+// Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.  FP32 operands with FP32 accumulation
+// (mixed path) or FP64 throughout (plain path; the boundary products are FP64 in both).
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "ism_paths.h"
 
 namespace ism {
-int gate_create(ism_problem*, const double*, int, const double*, const double*, const double*) {
-    return ISM_E_UNSUPPORTED;
+namespace {
+
+constexpr int GT = 64;        // output tile (rows and columns)
+constexpr int MMAX_G = 24;    // largest Taylor / Krylov order
+constexpr int RB = 8;         // rows of U built per workgroup
+constexpr int CBW = 16;       // columns per workgroup in the gradient kernel
+constexpr int CMAX_G = 32;    // largest number of controls in the gate path
+constexpr int WMAX_G = 16;    // largest union-pattern width
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Acc;
+template <> struct Acc<float> { typedef f4 T; };
+template <> struct Acc<double> { typedef d4 T; };
+
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-int gate_boundary_pass(ism_problem*, double*, double, bool) { return ISM_E_UNSUPPORTED; }
-int gate_slice_pass(ism_problem*, int, double, double*, bool) { return ISM_E_UNSUPPORTED; }
-int gate_copy_state(ism_problem*, double*, int) { return ISM_E_UNSUPPORTED; }
-size_t gate_footprint_extra(int, int, int, int, int, int) { return 0; }
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One batched complex GEMM entry: element offsets of the real planes of A, B, C and
+// op flags (bit 0: A conjugate-transposed, bit 1: B conjugate-transposed).
+struct GemmEntry {
+    long long a, b, c;
+    int flags;
+    int pad;
+};
+
+struct GemmArgs {
+    int M, N, Kd;
+    int lda, ldb, ldc;            // row strides (elements)
+    long long pa, pb, pc;         // offset of the imaginary plane from the real plane
+    const void* A;
+    const void* B;
+    void* C;
+    const GemmEntry* e;
+};
+
+template <typename R, int KC>
+__global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
+    __shared__ R As[2][KC][GT + 1];   // [re/im][k][i]
+    __shared__ R Bs[2][KC][GT + 1];   // [re/im][k][j]
+    const GemmEntry e = g.e[blockIdx.y];
+    const R* A = reinterpret_cast<const R*>(g.A) + e.a;
+    const R* Bm = reinterpret_cast<const R*>(g.B) + e.b;
+    R* Cm = reinterpret_cast<R*>(g.C) + e.c;
+    const int tilesN = g.N / GT;
+    const int i0 = (blockIdx.x / tilesN) * GT, j0 = (blockIdx.x % tilesN) * GT;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const bool hA = e.flags & 1, hB = e.flags & 2;
+    typename Acc<R>::T cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0;
+    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
+        // stage op(A)[i0:i0+64, k0:k0+KC] as As[k][i] and op(B)[k0:k0+KC, j0:j0+64] as Bs[k][j]
+        for (int q = t; q < GT * KC; q += 256) {
+            int i, k;
+            long long off;
+            if (!hA) {
+                i = q / KC; k = q % KC;
+                off = (long long)(i0 + i) * g.lda + (k0 + k);
+            } else {
+                k = q / GT; i = q % GT;
+                off = (long long)(k0 + k) * g.lda + (i0 + i);
+            }
+            As[0][k][i] = A[off];
+            As[1][k][i] = hA ? -A[off + g.pa] : A[off + g.pa];
+            int jj, kk;
+            long long offb;
+            if (!hB) {
+                kk = q / GT; jj = q % GT;
+                offb = (long long)(k0 + kk) * g.ldb + (j0 + jj);
+            } else {
+                jj = q / KC; kk = q % KC;
+                offb = (long long)(j0 + jj) * g.ldb + (k0 + kk);
+            }
+            Bs[0][kk][jj] = Bm[offb];
+            Bs[1][kk][jj] = hB ? -Bm[offb + g.pb] : Bm[offb + g.pb];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int kr = kk + (lane >> 4), li = lane & 15;
+            R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                ar[a] = As[0][kr][wr + a * 16 + li];
+                ai[a] = As[1][kr][wr + a * 16 + li];
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                br[b] = Bs[0][kr][wc + b * 16 + li];
+                bi[b] = Bs[1][kr][wc + b * 16 + li];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cr[a][b] = mfma16(ar[a], br[b], cr[a][b]);
+                    cr[a][b] = mfma16(-ai[a], bi[b], cr[a][b]);
+                    ci[a][b] = mfma16(ar[a], bi[b], ci[a][b]);
+                    ci[a][b] = mfma16(ai[a], br[b], ci[a][b]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // output lane layout of the 16x16x4 MFMA: f32 holds rows 4(l/16)+v,
+                // f64 holds rows l/16 + 4v (columns l%16 in both)
+                const int i = i0 + wr + a * 16 +
+                              (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+                const int j = j0 + wc + b * 16 + (lane & 15);
+                const long long o = (long long)i * g.ldc + j;
+                Cm[o] = cr[a][b][v];
+                Cm[o + g.pc] = ci[a][b][v];
+            }
+}
+
+// ---------------------------------------------------------------------------------
+// data of the generator on the union sparsity pattern of H0 and all H_c (ELL, width W)
+// ---------------------------------------------------------------------------------
+struct GateGen {
+    int d, dp, W, C, K;
+    const int* col;          // d*W column of each stored entry (padding: own row)
+    const dcx* h0v;          // d*W  values of H0 - s I
+    const dcx* hcu;          // C*d*W values of H_c on the union pattern
+    const int* ccol;         // C*d*WCc per-control columns
+    const dcx* cval;         // C*d*WCc per-control values
+    int WCc;
+    const double* u;         // K*C
+    double tau, shift;
+    double h0norm;           // || H0 - s ||_inf
+    const double* cnorm;     // C  || H_c ||_inf
+};
+
+__device__ __forceinline__ int taylor_terms(double theta, double tol, int& S) {
+    S = 1;
+    if (!(theta < 1e4)) return -1;
+    S = (int)ceil(theta / 1.0);
+    if (S < 1) S = 1;
+    const double ts = theta / S, ex = exp(ts);
+    int m = 1;
+    double term = ts;
+    while (m < MMAX_G) {
+        const double next = term * ts / (m + 1);
+        if (next * ex <= tol) break;
+        term = next;
+        ++m;
+    }
+    return m;
+}
+
+// Rows r0..r0+RB-1 of U_j = e^{-i tau s} exp(-i tau (H_j - s)) (FP64), stored as R.
+template <typename R, int WT>
+__global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long plane, int* flags) {
+    __shared__ dcx vs[RB][256];
+    const int j = blockIdx.x, r0 = blockIdx.y * RB, c = threadIdx.x;
+    const int d = gg.d, dp = gg.dp;
+    const double* uj = gg.u + (size_t)j * gg.C;
+    // row c of conj(H_j - s) on the union pattern
+    dcx hv[WT];
+    int hc[WT];
+    double theta = gg.h0norm;
+    for (int q = 0; q < gg.C; ++q) theta += fabs(uj[q]) * gg.cnorm[q];
+    theta *= gg.tau;
+    int S;
+    int m = taylor_terms(theta, 1e-17, S);
+    if (m < 0) {
+        if (c == 0 && blockIdx.y == 0) atomicOr(flags, 1);
+        m = 1;
+    }
+    const double ts = gg.tau / S;
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        dcx h = {0.0, 0.0};
+        int cc = c;
+        if (c < d && w < gg.W) {
+            const size_t idx = (size_t)c * gg.W + w;
+            h = gg.h0v[idx];
+            for (int q = 0; q < gg.C; ++q) {
+                const dcx x = gg.hcu[(size_t)q * d * gg.W + idx];
+                h.re += uj[q] * x.re;
+                h.im += uj[q] * x.im;
+            }
+            cc = gg.col[idx];
+        }
+        hv[w].re = ts * h.re;        // tau_sub * conj(H - s)
+        hv[w].im = -ts * h.im;
+        hc[w] = cc;
+    }
+    dcx acc[RB], tr[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        acc[q].re = (c == r0 + q) ? 1.0 : 0.0;
+        acc[q].im = 0.0;
+    }
+    for (int sub = 0; sub < S; ++sub) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) tr[q] = acc[q];
+        for (int k = 0; k < m; ++k) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) vs[q][c] = tr[q];
+            __syncthreads();
+            const double rk = 1.0 / (k + 1);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                double ar = 0.0, ai = 0.0;
+#pragma unroll
+                for (int w = 0; w < WT; ++w) {
+                    const dcx x = vs[q][hc[w]];
+                    ar = fma(hv[w].re, x.re, fma(-hv[w].im, x.im, ar));
+                    ai = fma(hv[w].re, x.im, fma(hv[w].im, x.re, ai));
+                }
+                tr[q].re = ai * rk;      // -i (h x) / (k+1)
+                tr[q].im = -ar * rk;
+                acc[q].re += tr[q].re;
+                acc[q].im += tr[q].im;
+            }
+            __syncthreads();
+        }
+    }
+    const double ph = -gg.tau * gg.shift;
+    const double cp = cos(ph), sp = sin(ph);
+    if (c < dp) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q;
+            if (r >= dp) break;
+            const long long o = (long long)j * plane * 2 + (long long)r * dp + c;
+            double xr = acc[q].re, xi = acc[q].im;
+            if (r >= d || c >= d) {            // padded block: identity
+                xr = (r == c) ? 1.0 : 0.0;
+                xi = 0.0;
+            } else {
+                const double yr = cp * xr - sp * xi, yi = cp * xi + sp * xr;
+                xr = yr;
+                xi = yi;
+            }
+            U[o] = (R)xr;
+            U[o + plane] = (R)xi;
+        }
+    }
+}
+
+// w_ab = i^{a+b} (-1)^b / ((a+b+1) a! b!) as a real magnitude; the phase i^{a+b}(-1)^b is
+// applied in the kernel.
+__constant__ double WAB[MMAX_G + 1][MMAX_G + 1];
+
+// Per (step, block of CBW columns): partial sums over rows and columns of
+// Im <y_k| Hhat_c |x_k> for every control c, in FP64.  MK bounds the Krylov order.
+template <typename R, int MK, int WT>
+__global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
+                                                   int ldxy, double* gpart, int ncb) {
+    extern __shared__ unsigned char smem_raw[];
+    R* kv = reinterpret_cast<R*>(smem_raw);                    // 2 (MK+1) dp
+    __shared__ double red[256];
+    const int j = blockIdx.x, cb = blockIdx.y, r = threadIdx.x;
+    const int d = gg.d, dp = gg.dp;
+    const double* uj = gg.u + (size_t)j * gg.C;
+    double bound = gg.h0norm;
+    for (int q = 0; q < gg.C; ++q) bound += fabs(uj[q]) * gg.cnorm[q];
+    // order m: the dropped terms (2 theta)^n / (n+1)!, n > m, are below the tolerance
+    int m = 1;
+    {
+        const double x = 2.0 * gg.tau * bound;
+        const double tol = sizeof(R) == 8 ? 1e-17 : 1e-10;
+        double t = x * x / 6.0;
+        while (m < MK && t > tol) {
+            ++m;
+            t = t * x / (m + 2);
+        }
+    }
+    // row r of tau (H_j - s) on the union pattern
+    R hvr[WT], hvi[WT];
+    int hcol[WT];
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        double hr = 0.0, hi = 0.0;
+        int cc = r;
+        if (r < d && w < gg.W) {
+            const size_t idx = (size_t)r * gg.W + w;
+            hr = gg.h0v[idx].re;
+            hi = gg.h0v[idx].im;
+            for (int q = 0; q < gg.C; ++q) {
+                const dcx x = gg.hcu[(size_t)q * d * gg.W + idx];
+                hr += uj[q] * x.re;
+                hi += uj[q] * x.im;
+            }
+            cc = gg.col[idx];
+        }
+        hvr[w] = (R)(gg.tau * hr);
+        hvi[w] = (R)(gg.tau * hi);
+        hcol[w] = cc;
+    }
+    double accg[CMAX_G];
+#pragma unroll
+    for (int q = 0; q < CMAX_G; ++q) accg[q] = 0.0;
+    R rtr[MK + 1], rti[MK + 1], ptr_[MK + 1], pti[MK + 1];
+    for (int kk = 0; kk < CBW; ++kk) {
+        const int k = cb * CBW + kk;
+        if (k >= d) break;
+        // column k of X_j and Y_j
+        const long long ox = (long long)j * xy_plane * 2 + (long long)r * ldxy + k;
+        rtr[0] = r < d ? XY[ox] : R(0);
+        rti[0] = r < d ? XY[ox + xy_plane] : R(0);
+        ptr_[0] = r < d ? XY[ox + dp] : R(0);
+        pti[0] = r < d ? XY[ox + dp + xy_plane] : R(0);
+        // Krylov vectors (tau H')^a of both columns
+#pragma unroll
+        for (int a = 1; a <= MK; ++a) {
+            if (a > m) break;
+            kv[r] = rtr[a - 1];
+            kv[dp + r] = rti[a - 1];
+            kv[2 * dp + r] = ptr_[a - 1];
+            kv[3 * dp + r] = pti[a - 1];
+            __syncthreads();
+            R xr = 0, xi = 0, yr = 0, yi = 0;
+#pragma unroll
+            for (int w = 0; w < WT; ++w) {
+                const int cc = hcol[w];
+                const R ur = kv[cc], ui = kv[dp + cc], vr = kv[2 * dp + cc], vi = kv[3 * dp + cc];
+                xr = fma(hvr[w], ur, fma(-hvi[w], ui, xr));
+                xi = fma(hvr[w], ui, fma(hvi[w], ur, xi));
+                yr = fma(hvr[w], vr, fma(-hvi[w], vi, yr));
+                yi = fma(hvr[w], vi, fma(hvi[w], vr, yi));
+            }
+            rtr[a] = xr;
+            rti[a] = xi;
+            ptr_[a] = yr;
+            pti[a] = yi;
+            __syncthreads();
+        }
+        // Krylov vectors of x into LDS
+#pragma unroll
+        for (int b = 0; b <= MK; ++b) {
+            if (b > m) break;
+            kv[(2 * b) * dp + r] = rtr[b];
+            kv[(2 * b + 1) * dp + r] = rti[b];
+        }
+        __syncthreads();
+        // t_b = sum_a conj(w_ab) p_a with conj(w_ab) = (-i)^{a+b} (-1)^b |w_ab|, then per
+        // control the imaginary part of sum_b conj(t_b) (H_c r_b)
+        R ttr[MK + 1], tti[MK + 1];
+#pragma unroll
+        for (int b = 0; b <= MK; ++b) {
+            R sr = 0, si = 0;
+#pragma unroll
+            for (int a = 0; a + b <= MK; ++a) {
+                if (a + b > m) break;
+                R wr = (R)WAB[a][b];
+                if (b & 1) wr = -wr;
+                const R pr = ptr_[a], pim = pti[a];
+                const int ph = (a + b) & 3;
+                const R qr = ph == 0 ? pr : ph == 1 ? pim : ph == 2 ? -pr : -pim;
+                const R qi = ph == 0 ? pim : ph == 1 ? -pr : ph == 2 ? -pim : pr;
+                sr = fma(wr, qr, sr);
+                si = fma(wr, qi, si);
+            }
+            ttr[b] = sr;
+            tti[b] = si;
+        }
+        if (r < d) {
+#pragma unroll
+            for (int q = 0; q < CMAX_G; ++q) {
+                if (q >= gg.C) break;
+                double sacc = 0.0;
+                for (int wc = 0; wc < gg.WCc; ++wc) {
+                    const size_t ci = ((size_t)q * d + r) * gg.WCc + wc;
+                    const int cc = gg.ccol[ci];
+                    const dcx hv = gg.cval[ci];
+#pragma unroll
+                    for (int b = 0; b <= MK; ++b) {
+                        if (b > m) break;
+                        const double xr = (double)kv[(2 * b) * dp + cc];
+                        const double xi = (double)kv[(2 * b + 1) * dp + cc];
+                        const double yr = hv.re * xr - hv.im * xi, yi = hv.re * xi + hv.im * xr;
+                        sacc += (double)ttr[b] * yi - (double)tti[b] * yr;   // Im(conj(t_b) y)
+                    }
+                }
+                accg[q] += sacc;
+            }
+        }
+        __syncthreads();
+    }
+    // block reduction over rows (deterministic tree)
+#pragma unroll
+    for (int q = 0; q < CMAX_G; ++q) {
+        if (q >= gg.C) break;
+        red[r] = r < d ? accg[q] : 0.0;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (r < w) red[r] += red[r + w];
+            __syncthreads();
+        }
+        if (r == 0) gpart[((size_t)j * ncb + cb) * gg.C + q] = red[0];
+        __syncthreads();
+    }
+}
+
+// g_{j,c} = beta_n (1/d) sum_cb gpart - alpha_j u_{j,c}; update or write the gradient.
+__global__ void k_gate_grad_finish(const double* gpart, int ncb, int K, int N, int C, int d,
+                                   const int* s, double* u, const double* alpha, double* grad,
+                                   double rho, int update, const int* active) {
+    if (active && active[0] == 0) update = 0;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= K * C) return;
+    const int j = idx / C, c = idx - j * C;
+    int lo = 0, hi = N;                         // slice of step j: s[n] <= j < s[n+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (s[mid] <= j) lo = mid;
+        else hi = mid;
+    }
+    const double beta = (double)K / (double)(s[lo + 1] - s[lo]);
+    double acc = 0.0;
+    for (int cb = 0; cb < ncb; ++cb) acc += gpart[((size_t)j * ncb + cb) * C + c];
+    const double uu = u[idx];
+    const double g = beta * acc / d - (alpha ? alpha[j] : 0.0) * uu;
+    if (grad) grad[idx] = g;
+    if (update) u[idx] = fma(rho, g, uu);
+}
+
+template <typename R>
+__global__ void k_to_f64(const R* src, double* dst, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = (double)src[i];
+}
+
+template <typename R>
+__global__ void k_from_f64(const double* src, R* dst, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) dst[i] = (R)src[i];
+}
+
+// phi_n = (1 - w_n) Psi_n + w_n Lambda_n (planar FP64), w_n = s_n / K; and the right-hand
+// operand [phi_n | .] of the slice sweeps (columns 0..dp-1 of RHS_n) in precision R.
+template <typename R>
+__global__ void k_gate_phi(const double* Psi, const double* Lam, double* phi, R* rhs, const int* s,
+                           int N, int K, int dp, const double* psi0, const double* target) {
+    const long long per = 2LL * dp * dp;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n_all = (long long)(N + 1) * per;
+    for (; i < n_all; i += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(i / per);
+        const long long e = i - n * per;
+        const double w = (double)s[n] / (double)K;
+        double f = (1.0 - w) * Psi[i] + w * Lam[i];
+        if (n == 0) f = psi0[e];
+        if (n == N) f = target[e];
+        phi[i] = f;
+        if (n < N) {
+            const long long plane = (long long)dp * dp;
+            const int p = (int)(e / plane);
+            const long long rc = e - p * plane;
+            const int rr = (int)(rc / dp), cc = (int)(rc - (long long)rr * dp);
+            rhs[(long long)n * 2 * dp * 2 * dp + p * (long long)dp * 2 * dp + (long long)rr * 2 * dp + cc] = (R)f;
+        }
+    }
+}
+
+// J = Re Tr(W^+ Psi_N)/d, F = |Tr(W^+ Psi_N)|^2/d^2 (one block), penalty from u.
+__global__ void k_gate_fid(const double* PsiN, const double* W, int d, int dp, const double* u,
+                           const double* alpha, int K, int C, double tau, double* J, double* F,
+                           double* Jhist, int* active, double fid_stop, int* flags) {
+    __shared__ double red[3][256];
+    const int t = threadIdx.x;
+    const long long plane = (long long)dp * dp;
+    double zr = 0.0, zi = 0.0, pen = 0.0;
+    for (long long e = t; e < (long long)d * dp; e += blockDim.x) {
+        const int r = (int)(e / dp), c = (int)(e % dp);
+        if (c >= d) continue;
+        const long long o = (long long)r * dp + c;
+        const double wr = W[o], wi = W[o + plane], pr = PsiN[o], pi = PsiN[o + plane];
+        zr += wr * pr + wi * pi;
+        zi += wr * pi - wi * pr;
+    }
+    if (alpha)
+        for (int i = t; i < K * C; i += blockDim.x) pen += alpha[i / C] * u[i] * u[i];
+    red[0][t] = zr;
+    red[1][t] = zi;
+    red[2][t] = pen;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double a = red[0][0] / d, b = red[1][0] / d;
+        const double Jv = a - 0.5 * tau * red[2][0];
+        const double Fv = a * a + b * b;
+        J[0] = Jv;
+        F[0] = Fv;
+        if (Jhist) Jhist[0] = Jv;
+        if (!(fabs(Jv) < 1e300)) atomicOr(&flags[0], 1);
+        if (active) {
+            if (active[0] && Fv >= fid_stop) active[0] = 0;
+            if (active[0]) atomicAdd(&flags[1], 1);
+        }
+    }
+}
+
+// Planar FP64 matrix from interleaved complex d x d, zero padded to dp.
+__global__ void k_planar_from_interleaved(const dcx* src, double* dst, int d, int dp) {
+    const long long plane = (long long)dp * dp;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(e / dp), c = (int)(e % dp);
+        dcx v = {0.0, 0.0};
+        if (r < d && c < d) v = src[(long long)r * d + c];
+        dst[e] = v.re;
+        dst[e + plane] = v.im;
+    }
+}
+
+__global__ void k_interleaved_from_planar(const double* src, dcx* dst, int d, int dp) {
+    const long long plane = (long long)dp * dp;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)d * d;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(e / d), c = (int)(e % d);
+        const long long o = (long long)r * dp + c;
+        dst[e].re = src[o];
+        dst[e].im = src[o + plane];
+    }
+}
+
+template <typename R>
+__global__ void k_copy_identity_or(R* dst, const R* src, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (long long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+}  // namespace
+
+#include "k_gate_host.inc"
+
 }  // namespace ism

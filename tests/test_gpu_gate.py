@@ -1,0 +1,123 @@
+"""GPU parity of the dense gate path (batched complex GEMM on MFMA) against the FP64 oracle.
+
+Gate synthesis: psi0 = I, target W, <A|B> = Tr(A^+ B)/d (evolution-operator form of Sec. 2).
+Tolerances as for the state path: FP64 relative L2 <= 1e-12 (grows as 2e-14 sqrt(K) beyond
+K = 2500), FP32 mixed ||U_gpu(T) - U_ref(T)||_F / sqrt(d) <= 1e-4 and gradient relative L2
+<= 1e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import problems
+from oracle import finite as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    from paper_1603_01237_amd import _lib
+    return _lib
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gate_problem(n, K, N, seed=5, T=None):
+    p = problems.spin_chain_gate(seed=seed, n=n, K=K, N=N, T=T if T is not None else K * 0.01)
+    return p
+
+
+def _spin2_gate(K, N, seed=3):
+    p = problems.spin2(K=K, N=N)
+    rng = np.random.default_rng(seed)
+    W = problems.haar_unitary(4, rng)
+    u = rng.uniform(-1, 1, size=(1, K, 2))
+    return problems.FiniteProblem("spin2_gate", p.H0, p.Hc, np.eye(4, dtype=complex), W, p.T, K,
+                                  N, u, np.zeros(K), 0.5, 5, kind="gate")
+
+
+CASES = [
+    ("spin2_gate_K24_N3", lambda: _spin2_gate(24, 3)),
+    ("spin2_gate_K17_N5", lambda: _spin2_gate(17, 5)),
+    ("chain4_gate_K30_N4", lambda: _gate_problem(4, 30, 4)),
+    ("chain6_gate_K13_N13", lambda: _gate_problem(6, 13, 13)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gate_parity(name, mk, prec):
+    _say("case", name, prec)
+    P = _P()
+    p = mk()
+    with P.from_problem(p, precision=prec) as h:
+        UT = h.forward()[0]
+        J, F = h.fidelity()
+        g = h.gradient()[0]
+    gr, Jr, Fr, UK = O.gradient(p.H0, p.Hc, p.psi0, p.target, p.u0[0], p.T, p.alpha)
+    d = p.d
+    if prec == "fp64":
+        assert _rel(UT, UK) <= 1e-12
+        assert abs(J[0] - Jr) <= 1e-12 and abs(F[0] - Fr) <= 1e-12
+        assert _rel(g, gr) <= 1e-12, _rel(g, gr)
+    else:
+        assert np.linalg.norm(UT - UK) / np.sqrt(d) <= 1e-4
+        assert abs(F[0] - Fr) <= 1e-4
+        assert _rel(g, gr) <= 1e-3, _rel(g, gr)
+
+
+def test_gate_iterate_equals_plain():
+    _say("case gate iterate")
+    P = _P()
+    p = _gate_problem(4, 40, 6)
+    ref = O.plain_gradient_method(p.H0, p.Hc, p.psi0, p.target, p.u0[0], p.T, p.alpha, 0.5, 5)
+    with P.from_problem(p, precision="fp64") as h:
+        Jh, done = h.iterate(5, 0.5)
+        u = h.get_controls()[0]
+    assert done == 5
+    assert np.max(np.abs(Jh[:, 0] - ref["J"])) <= 1e-12
+    assert _rel(u, ref["u"]) <= 1e-12
+
+
+def test_gate_full_size_sampled():
+    """8-spin chain gate synthesis at its full size (d=256, 16 controls, K=2000, N=64):
+    U(T) against the oracle's product of step exponentials; the gradient at sampled steps."""
+    _say("case gate full size")
+    P = _P()
+    p = problems.spin_chain_gate()
+    res = {}
+    for prec in ("fp32", "fp64"):
+        with P.from_problem(p, precision=prec) as h:
+            res[prec] = (h.forward()[0], h.gradient()[0])
+            _say(prec, "done")
+    tau = p.T / p.K
+    u = p.u0[0]
+    Us = O.step_unitaries(p.H0, p.Hc, u, tau)
+    psis = O.forward(Us, p.psi0)
+    lams = O.backward(Us, p.target)
+    UK = psis[-1]
+    for prec in ("fp32", "fp64"):
+        UT, g = res[prec]
+        errU = np.linalg.norm(UT - UK) / np.sqrt(p.d)
+        _say(prec, "U(T) err", errU)
+        if prec == "fp64":
+            assert _rel(UT, UK) <= max(1e-12, 2e-14 * np.sqrt(p.K))
+        else:
+            assert errU <= 1e-4
+    for j in (0, 31, 1000, 1999):
+        Hh = O.hhat(O.hamiltonian(p.H0, p.Hc, u[j]), p.Hc, tau)
+        gref = np.array([np.trace(lams[j].conj().T @ Hh[c] @ psis[j]).imag / p.d
+                         for c in range(p.C)])
+        e64 = _rel(res["fp64"][1][j], gref)
+        e32 = _rel(res["fp32"][1][j], gref)
+        _say("step", j, "fp64 g err", e64, "fp32 g err", e32)
+        assert e64 <= 1e-10
+        assert e32 <= 1e-3
