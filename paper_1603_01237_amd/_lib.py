@@ -131,12 +131,14 @@ class Problem:
     controls, gradients and states are exchanged as device tensors (torch.cuda),
     passed by pointer."""
 
-    def __init__(self, handle, shape_state, d, C, K, N, B, io_device, gpe_n=0):
+    def __init__(self, handle, shape_state, d, C, K, N, B, io_device, gpe_n=0, T=1.0):
         self._h = handle
         self.state_shape = shape_state
         self.d, self.C, self.K, self.N, self.B = d, C, K, N, B
+        self.T = float(T)
         self.io_device = io_device
         self.gpe_n = gpe_n
+        self.version = 0          # incremented whenever the controls are set
 
     # ------------------------------------------------------------------ creation
     @classmethod
@@ -170,7 +172,7 @@ class Problem:
         _check(L.ism_problem_create(ct.byref(h), d, C, _cptr(H0), _cptr(Hc), _cptr(psi0),
                                     _cptr(target), float(T), int(K), int(N), ct.byref(o)),
                "ism_problem_create")
-        return cls(h, sshape, d, C, int(K), int(N), int(batch), io_device)
+        return cls(h, sshape, d, C, int(K), int(N), int(batch), io_device, T=T)
 
     @classmethod
     def create_gpe(cls, n, L_box, g, V0, V1, V2, psi0, target, T, K, N, precision="fp64",
@@ -192,7 +194,7 @@ class Problem:
                                         _cptr(V1), float(V2), _cptr(psi0), _cptr(target),
                                         float(T), int(K), int(N), ct.byref(o)),
                "ism_problem_create_gpe")
-        return cls(h, (n,), n, 1, int(K), int(N), int(batch), io_device, gpe_n=n)
+        return cls(h, (n,), n, 1, int(K), int(N), int(batch), io_device, gpe_n=n, T=T)
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -232,6 +234,7 @@ class Problem:
 
     # ------------------------------------------------------------------ API
     def set_controls(self, u):
+        self.version += 1
         if self.io_device:
             if tuple(u.shape) != (self.B, self.K, self.C) or not u.is_contiguous():
                 raise ValueError("controls must be a contiguous (B, K, C) float64 device tensor")

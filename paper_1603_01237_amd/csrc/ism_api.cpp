@@ -192,7 +192,7 @@ static SpArgs sp_args(ism_problem* p, int assemble) {
     a.C = p->C;
     a.CG = p->CG;
     a.WC = p->WC;
-    a.P = 64 / p->d;
+    a.P = p->d <= 64 ? 64 / p->d : 1;     // items per wavefront (one item per workgroup beyond 64 rows)
     a.items_per_inst = assemble ? p->N * p->d : p->N;
     a.waves_per_inst = (a.items_per_inst + a.P - 1) / a.P;
     a.LMAX = (p->K + p->N - 1) / p->N;
@@ -480,8 +480,7 @@ int ism_problem_create(ism_problem** out, int d, int n_ctrl, const double* H0, c
             st = gate_create(p, H0, o.h0_batched, Hc, psi0, target);
         } else {
             p->path = PATH_SPARSE;
-            if (d > 64) st = ISM_E_UNSUPPORTED;
-            else st = sp_create(p, H0, o.h0_batched, Hc, psi0, target);
+            st = sp_create(p, H0, o.h0_batched, Hc, psi0, target);
         }
     }
     if (st) {

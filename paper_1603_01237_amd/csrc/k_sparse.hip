@@ -13,9 +13,9 @@
 //
 // Step map.  exp(-i tau H) = e^{-i tau s} exp(-i tau (H - s)) with a scalar shift s per
 // instance (midpoint of the diagonal of H0).  The kernels apply only the shifted
-// factor, as a truncated Taylor series of its action on the vector (S sub-steps of
-// tau/S, m terms each, m and S per instance from a norm bound so that the truncation
-// is below rounding).  The scalar phase e^{-i tau s L_n} of a whole slice is put back
+// factor, as a truncated Taylor polynomial of its action on the vector evaluated by
+// Horner's rule (S sub-steps of tau/S, degree m, m and S per instance from a norm bound
+// so that the truncation is below rounding).  The scalar phase e^{-i tau s L_n} of a whole slice is put back
 // once, in FP64: on the slice propagator in the boundary kernel and on the gradient
 // overlaps in the slice kernel.  Unitarity is therefore never broken by a rounded
 // per-step phase.
@@ -69,8 +69,50 @@ __device__ __forceinline__ double lane_fetch(int addr, double v) {
                                             (unsigned long long)(unsigned)lo));
 }
 
+// Row exchange between the lanes that hold one item.
+//  XWave : d <= 64, several items per wavefront; a neighbour row is read straight from the
+//          other lane's register (ds_bpermute), so publish/sync are no-ops and `addr` is the
+//          lane's byte address.
+//  XBlock: 64 < d <= 256, one item per workgroup; rows are published to LDS slots, the
+//          workgroup synchronises, and `addr` is the row index.
+template <typename R>
+struct XWave {
+    static constexpr bool kBlock = false;
+    __device__ __forceinline__ void publish(int, int, R) const {}
+    __device__ __forceinline__ void sync() const {}
+    __device__ __forceinline__ R fetch(int, int addr, R v) const { return lane_fetch(addr, v); }
+};
+template <typename R>
+struct XBlock {
+    static constexpr bool kBlock = true;
+    R* lds;
+    int ld;
+    __device__ __forceinline__ void publish(int slot, int r, R v) const { lds[slot * ld + r] = v; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+    __device__ __forceinline__ R fetch(int slot, int addr, R) const { return lds[slot * ld + addr]; }
+};
+
+// Diagonal entry tau_sub (H0_rr - s) of the generator.  In FP32 it is carried as a pair
+// hi + lo: the rounding of a single FP32 value would be the same at every step and shift
+// the phase of that row coherently over a sweep (about 1e-8 per step, 1.5e-4 after 20000
+// steps of the rotor); the pair keeps the product accurate to ~1e-14 relative.
+template <typename R>
+struct Diag {
+    R h, l;
+    __device__ __forceinline__ static Diag make(double x) {
+        Diag d;
+        d.h = (R)x;
+        d.l = (R)(x - (double)d.h);
+        return d;
+    }
+    __device__ __forceinline__ R mul(R t) const {
+        if (sizeof(R) == 8) return h * t;
+        return fma(l, t, h * t);
+    }
+};
+
 // Generator terms of one row: H - s = diag + sum_g v_g G_g, G_g stored as WCM entries
-// per row (lane address of the column, pre-scaled value).
+// per row (exchange address of the column, pre-scaled value).
 template <typename R, int CGM, int WCM, bool RH>
 struct Gen {
     int addr[CGM][WCM];
@@ -78,16 +120,16 @@ struct Gen {
     R vim[CGM][WCM];
 };
 
-template <typename R, int CGM, int WCM, bool RH>
-__device__ __forceinline__ void gen_apply(const Gen<R, CGM, WCM, RH>& G, R xr, R xi, R (&tr)[CGM],
-                                          R (&ti)[CGM]) {
+template <typename R, int CGM, int WCM, bool RH, class X>
+__device__ __forceinline__ void gen_apply(const Gen<R, CGM, WCM, RH>& G, const X& ex, int slot,
+                                          R xr, R xi, R (&tr)[CGM], R (&ti)[CGM]) {
 #pragma unroll
     for (int g = 0; g < CGM; ++g) {
         R ar = 0, ai = 0;
 #pragma unroll
         for (int w = 0; w < WCM; ++w) {
-            const R nr = lane_fetch(G.addr[g][w], xr);
-            const R ni = lane_fetch(G.addr[g][w], xi);
+            const R nr = ex.fetch(slot, G.addr[g][w], xr);
+            const R ni = ex.fetch(slot + 1, G.addr[g][w], xi);
             if (RH) {
                 ar = fma(G.vre[g][w], nr, ar);
                 ai = fma(G.vre[g][w], ni, ai);
@@ -101,54 +143,71 @@ __device__ __forceinline__ void gen_apply(const Gen<R, CGM, WCM, RH>& G, R xr, R
     }
 }
 
-// x <- exp(-i (H - s) tau_sub) x by m Taylor terms (generator pre-scaled by tau_sub).
-template <typename R, int CGM, int WCM, bool RH>
-__device__ __forceinline__ void fwd_substep(R& xr, R& xi, R d0, const R (&v)[CGM],
-                                            const Gen<R, CGM, WCM, RH>& G, int m) {
-    R ar = xr, ai = xi, tr = xr, ti = xi;
+// x <- exp(-i (H - s) tau_sub) x, degree-m Taylor polynomial evaluated by Horner's rule
+// p <- x + A p / k (k = m..1): the small high-order terms are combined before they meet x,
+// so they are not lost to the rounding of x (which in FP32 would shorten the series the same
+// way at every step).  The generator is pre-scaled by tau_sub.
+template <typename R, int CGM, int WCM, bool RH, class X>
+__device__ __forceinline__ void fwd_substep(R& xr, R& xi, Diag<R> d0, const R (&v)[CGM],
+                                            const Gen<R, CGM, WCM, RH>& G, const X& ex, int r,
+                                            int m) {
+    R pr = xr, pi = xi;
 #pragma unroll 1
-    for (int k = 0; k < m; ++k) {
+    for (int k = m; k >= 1; --k) {
+        ex.publish(0, r, pr);
+        ex.publish(1, r, pi);
+        ex.sync();
         R gr[CGM], gi[CGM];
-        gen_apply(G, tr, ti, gr, gi);
-        R hr = d0 * tr, hi = d0 * ti;
+        gen_apply(G, ex, 0, pr, pi, gr, gi);
+        ex.sync();
+        R hr = d0.mul(pr), hi = d0.mul(pi);
 #pragma unroll
         for (int g = 0; g < CGM; ++g) {
             hr = fma(v[g], gr[g], hr);
             hi = fma(v[g], gi[g], hi);
         }
-        const R rk = rk_of(R(0), k);
-        tr = hi * rk;        // t <- -i h / (k+1)
-        ti = -hr * rk;
-        ar += tr;
-        ai += ti;
+        const R rk = rk_of(R(0), k - 1);     // 1/k
+        pr = fma(hi, rk, xr);                // p <- x - i h / k
+        pi = fma(-hr, rk, xi);
     }
-    xr = ar;
-    xi = ai;
+    xr = pr;
+    xi = pi;
 }
 
 // One sub-step of the block exponential exp([[A^+, E^+],[0, A^+]]) with
 // A^+ = +i tau_sub (H - s), E_c^+ = +i tau_sub G_c, applied to (y_c, chi), and of
-// exp(A^+) applied to psi (reversal of the forward slice trajectory).
-template <typename R, int CGM, int WCM, bool RH>
+// exp(A^+) applied to psi (reversal of the forward slice trajectory); Horner's rule on the
+// block matrix: (p_y, p_x) <- (y, x) + (A^+ p_y + E^+ p_x, A^+ p_x) / k.
+template <typename R, int CGM, int WCM, bool RH, class X>
 __device__ __forceinline__ void adj_substep(R& cr, R& ci, R& pr, R& pi, R (&yr)[CGM], R (&yi)[CGM],
-                                            R d0, const R (&v)[CGM],
-                                            const Gen<R, CGM, WCM, RH>& G, int m) {
-    R acr = cr, aci = ci, tcr = cr, tci = ci;
-    R apr = pr, api = pi, tpr = pr, tpi = pi;
-    R ayr[CGM], ayi[CGM], tyr[CGM], tyi[CGM];
+                                            Diag<R> d0, const R (&v)[CGM],
+                                            const Gen<R, CGM, WCM, RH>& G, const X& ex, int r,
+                                            int m) {
+    R qcr = cr, qci = ci, qpr = pr, qpi = pi;
+    R qyr[CGM], qyi[CGM];
 #pragma unroll
     for (int c = 0; c < CGM; ++c) {
-        ayr[c] = tyr[c] = yr[c];
-        ayi[c] = tyi[c] = yi[c];
+        qyr[c] = yr[c];
+        qyi[c] = yi[c];
     }
 #pragma unroll 1
-    for (int k = 0; k < m; ++k) {
-        const R rk = rk_of(R(0), k);
+    for (int k = m; k >= 1; --k) {
+        const R rk = rk_of(R(0), k - 1);
+        ex.publish(0, r, qcr);
+        ex.publish(1, r, qci);
+        ex.publish(2, r, qpr);
+        ex.publish(3, r, qpi);
+#pragma unroll
+        for (int c = 0; c < CGM; ++c) {
+            ex.publish(4 + 2 * c, r, qyr[c]);
+            ex.publish(5 + 2 * c, r, qyi[c]);
+        }
+        ex.sync();
         R gcr[CGM], gci[CGM];
-        gen_apply(G, tcr, tci, gcr, gci);
+        gen_apply(G, ex, 0, qcr, qci, gcr, gci);
         R gpr[CGM], gpi[CGM];
-        gen_apply(G, tpr, tpi, gpr, gpi);
-        R hcr = d0 * tcr, hci = d0 * tci, hpr = d0 * tpr, hpi = d0 * tpi;
+        gen_apply(G, ex, 2, qpr, qpi, gpr, gpi);
+        R hcr = d0.mul(qcr), hci = d0.mul(qci), hpr = d0.mul(qpr), hpi = d0.mul(qpi);
 #pragma unroll
         for (int g = 0; g < CGM; ++g) {
             hcr = fma(v[g], gcr[g], hcr);
@@ -159,40 +218,35 @@ __device__ __forceinline__ void adj_substep(R& cr, R& ci, R& pr, R& pi, R (&yr)[
 #pragma unroll
         for (int c = 0; c < CGM; ++c) {
             R gyr[CGM], gyi[CGM];
-            gen_apply(G, tyr[c], tyi[c], gyr, gyi);
-            R hyr = fma(d0, tyr[c], gcr[c]), hyi = fma(d0, tyi[c], gci[c]);
+            gen_apply(G, ex, 4 + 2 * c, qyr[c], qyi[c], gyr, gyi);
+            R hyr = d0.mul(qyr[c]) + gcr[c], hyi = d0.mul(qyi[c]) + gci[c];
 #pragma unroll
             for (int g = 0; g < CGM; ++g) {
                 hyr = fma(v[g], gyr[g], hyr);
                 hyi = fma(v[g], gyi[g], hyi);
             }
-            tyr[c] = -hyi * rk;  // t <- +i h / (k+1)
-            tyi[c] = hyr * rk;
-            ayr[c] += tyr[c];
-            ayi[c] += tyi[c];
+            qyr[c] = fma(-hyi, rk, yr[c]);   // q <- y + i h / k
+            qyi[c] = fma(hyr, rk, yi[c]);
         }
-        tcr = -hci * rk;
-        tci = hcr * rk;
-        acr += tcr;
-        aci += tci;
-        tpr = -hpi * rk;
-        tpi = hpr * rk;
-        apr += tpr;
-        api += tpi;
+        ex.sync();
+        qcr = fma(-hci, rk, cr);
+        qci = fma(hcr, rk, ci);
+        qpr = fma(-hpi, rk, pr);
+        qpi = fma(hpr, rk, pi);
     }
-    cr = acr;
-    ci = aci;
-    pr = apr;
-    pi = api;
+    cr = qcr;
+    ci = qci;
+    pr = qpr;
+    pi = qpi;
 #pragma unroll
     for (int c = 0; c < CGM; ++c) {
-        yr[c] = ayr[c];
-        yi[c] = ayi[c];
+        yr[c] = qyr[c];
+        yi[c] = qyi[c];
     }
 }
 
-// Sum of v over the d lanes of this item; the result is valid on the item's row 0.
-__device__ __forceinline__ double item_sum(double v, int lane, int r, int d) {
+// Sum of v over the rows of this item; the result is valid on the item's row 0.
+__device__ __forceinline__ double item_sum(double v, int lane, int r, int d, const XWave<float>&) {
     for (int off = 1; off < d; off <<= 1) {
         const int src = lane + off < WAVE ? lane + off : WAVE - 1;
         const double o = lane_fetch(src * 4, v);
@@ -200,14 +254,40 @@ __device__ __forceinline__ double item_sum(double v, int lane, int r, int d) {
     }
     return v;
 }
+__device__ __forceinline__ double item_sum(double v, int lane, int r, int d, const XWave<double>& x) {
+    return item_sum(v, lane, r, d, XWave<float>());
+}
+template <typename R>
+__device__ __forceinline__ double item_sum(double v, int lane, int r, int d, const XBlock<R>&) {
+    __shared__ double red[4];
+    (void)r;
+    (void)d;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if (lane == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    return s;
+}
 
 struct ItemMap {
     int b, lane, p, r, item, base;
     bool valid;
 };
 
+template <class X>
 __device__ __forceinline__ bool map_item(const SpArgs& a, ItemMap& im) {
     im.lane = threadIdx.x & (WAVE - 1);
+    if (X::kBlock) {                      // one item per workgroup, rows on threads
+        im.b = blockIdx.y;
+        im.p = 0;
+        im.r = threadIdx.x;
+        im.item = blockIdx.x;
+        im.valid = im.r < a.d;
+        im.base = 0;
+        return true;
+    }
     int gw = blockIdx.x * WPB + (threadIdx.x >> 6);
     gw = __builtin_amdgcn_readfirstlane(gw);
     im.b = gw / a.waves_per_inst;
@@ -221,7 +301,7 @@ __device__ __forceinline__ bool map_item(const SpArgs& a, ItemMap& im) {
     return true;
 }
 
-template <typename R, int CGM, int WCM, bool RH>
+template <typename R, int CGM, int WCM, bool RH, class X>
 __device__ __forceinline__ void load_gen(const SpArgs& a, const ItemMap& im, double ts,
                                          Gen<R, CGM, WCM, RH>& G) {
 #pragma unroll
@@ -230,12 +310,13 @@ __device__ __forceinline__ void load_gen(const SpArgs& a, const ItemMap& im, dou
         for (int w = 0; w < WCM; ++w) {
             if (im.valid && g < a.CG && w < a.WC) {
                 const int idx = (g * a.d + im.r) * a.WC + w;
-                G.addr[g][w] = (im.base + a.gcol[idx]) * 4;
+                const int col = a.gcol[idx];
+                G.addr[g][w] = X::kBlock ? col : (im.base + col) * 4;
                 const dcx gv = a.gval[idx];
                 G.vre[g][w] = (R)(gv.re * ts);
                 G.vim[g][w] = (R)(gv.im * ts);
             } else {
-                G.addr[g][w] = im.lane * 4;
+                G.addr[g][w] = X::kBlock ? 0 : im.lane * 4;
                 G.vre[g][w] = 0;
                 G.vim[g][w] = 0;
             }
@@ -258,20 +339,42 @@ __device__ __forceinline__ void load_controls(const SpArgs& a, int b, int j, R (
     }
 }
 
-template <typename R, int CGM, int WCM, bool RH>
-__global__ __launch_bounds__(WAVE * WPB) void k_sp_assemble(SpArgs a) {
+template <typename R, class X>
+__device__ __forceinline__ X make_exchange(unsigned char* smem);
+template <>
+__device__ __forceinline__ XWave<float> make_exchange<float, XWave<float>>(unsigned char*) {
+    return XWave<float>();
+}
+template <>
+__device__ __forceinline__ XWave<double> make_exchange<double, XWave<double>>(unsigned char*) {
+    return XWave<double>();
+}
+template <>
+__device__ __forceinline__ XBlock<float> make_exchange<float, XBlock<float>>(unsigned char* s) {
+    return XBlock<float>{reinterpret_cast<float*>(s), (int)blockDim.x};
+}
+template <>
+__device__ __forceinline__ XBlock<double> make_exchange<double, XBlock<double>>(unsigned char* s) {
+    return XBlock<double>{reinterpret_cast<double*>(s), (int)blockDim.x};
+}
+
+template <typename R, int CGM, int WCM, bool RH, class X>
+__global__ __launch_bounds__(256) void k_sp_assemble(SpArgs a) {
+    extern __shared__ unsigned char sp_smem[];
     ItemMap im;
-    if (!map_item(a, im)) return;
+    if (!map_item<X>(a, im)) return;
+    const X ex = make_exchange<R, X>(sp_smem);
     const TaylorP tp = a.tp[im.b];
     const int m = __builtin_amdgcn_readfirstlane(tp.m);
     const int S = __builtin_amdgcn_readfirstlane(tp.S);
     Gen<R, CGM, WCM, RH> G;
-    load_gen(a, im, tp.tau_sub, G);
+    load_gen<R, CGM, WCM, RH, X>(a, im, tp.tau_sub, G);
     const double sh = a.shift[im.b];
-    const R d0 = im.valid ? (R)((a.h0diag[(size_t)im.b * a.h0diag_stride + im.r] - sh) * tp.tau_sub)
-                          : R(0);
-    const int n = im.valid ? im.item / a.d : 0;
-    const int col = im.valid ? im.item - n * a.d : 0;
+    const Diag<R> d0 = Diag<R>::make(
+        im.valid ? (a.h0diag[(size_t)im.b * a.h0diag_stride + im.r] - sh) * tp.tau_sub : 0.0);
+    const bool item_ok = X::kBlock ? true : im.valid;
+    const int n = item_ok ? im.item / a.d : 0;
+    const int col = item_ok ? im.item - n * a.d : 0;
     const int sn = a.s[n], L = a.s[n + 1] - sn;
     R xr = (im.valid && im.r == col) ? R(1) : R(0), xi = 0;
     for (int jl = 0; jl < a.LMAX; ++jl) {
@@ -281,7 +384,7 @@ __global__ __launch_bounds__(WAVE * WPB) void k_sp_assemble(SpArgs a) {
         double ud[CGM];
         load_controls(a, im.b, j, v, ud);
         R nr = xr, ni = xi;
-        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, v, G, m);
+        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, v, G, ex, im.r, m);
         if (act) {
             xr = nr;
             xi = ni;
@@ -295,19 +398,22 @@ __global__ __launch_bounds__(WAVE * WPB) void k_sp_assemble(SpArgs a) {
     }
 }
 
-template <typename R, int CGM, int WCM, bool RH>
-__global__ __launch_bounds__(WAVE * WPB) void k_sp_slice(SpArgs a) {
+template <typename R, int CGM, int WCM, bool RH, class X>
+__global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
+    extern __shared__ unsigned char sp_smem[];
     ItemMap im;
-    if (!map_item(a, im)) return;
+    if (!map_item<X>(a, im)) return;
+    const X ex = make_exchange<R, X>(sp_smem);
     const TaylorP tp = a.tp[im.b];
     const int m = __builtin_amdgcn_readfirstlane(tp.m);
     const int S = __builtin_amdgcn_readfirstlane(tp.S);
     Gen<R, CGM, WCM, RH> G;
-    load_gen(a, im, tp.tau_sub, G);
+    load_gen<R, CGM, WCM, RH, X>(a, im, tp.tau_sub, G);
     const double sh = a.shift[im.b];
-    const R d0 = im.valid ? (R)((a.h0diag[(size_t)im.b * a.h0diag_stride + im.r] - sh) * tp.tau_sub)
-                          : R(0);
-    const int n = im.valid ? im.item : 0;
+    const Diag<R> d0 = Diag<R>::make(
+        im.valid ? (a.h0diag[(size_t)im.b * a.h0diag_stride + im.r] - sh) * tp.tau_sub : 0.0);
+    const bool item_ok = X::kBlock ? true : im.valid;
+    const int n = item_ok ? im.item : 0;
     const int sn = a.s[n], L = a.s[n + 1] - sn;
     const size_t pb = ((size_t)im.b * (a.N + 1)) * a.d;
     R xr = 0, xi = 0;
@@ -324,7 +430,7 @@ __global__ __launch_bounds__(WAVE * WPB) void k_sp_slice(SpArgs a) {
         double ud[CGM];
         load_controls(a, im.b, j, v, ud);
         R nr = xr, ni = xi;
-        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, v, G, m);
+        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, v, G, ex, im.r, m);
         if (act) {
             xr = nr;
             xi = ni;
@@ -352,7 +458,8 @@ __global__ __launch_bounds__(WAVE * WPB) void k_sp_slice(SpArgs a) {
 #pragma unroll
         for (int c = 0; c < CGM; ++c) yr[c] = yi[c] = 0;
         R ncr = cr, nci = ci, npr = pr, npi = pi;
-        for (int sub = 0; sub < S; ++sub) adj_substep(ncr, nci, npr, npi, yr, yi, d0, v, G, m);
+        for (int sub = 0; sub < S; ++sub)
+            adj_substep(ncr, nci, npr, npi, yr, yi, d0, v, G, ex, im.r, m);
         if (act) {
             cr = ncr;
             ci = nci;
@@ -363,13 +470,13 @@ __global__ __launch_bounds__(WAVE * WPB) void k_sp_slice(SpArgs a) {
 #pragma unroll
         for (int c = 0; c < CGM; ++c) {
             if (c >= a.C) break;
-            // <y_c | psi_j> in FP64
+            // <y_c | psi_j> in FP64 (rows beyond d hold zeros)
             const double yre = (double)yr[c], yim = (double)yi[c];
             const double qre = (double)pr, qim = (double)pi;
             double ore = fma(yre, qre, yim * qim);
             double oim = fma(yre, qim, -yim * qre);
-            ore = item_sum(ore, im.lane, im.r, a.d);
-            oim = item_sum(oim, im.lane, im.r, a.d);
+            ore = item_sum(ore, im.lane, im.r, a.d, ex);
+            oim = item_sum(oim, im.lane, im.r, a.d, ex);
             if (act && im.r == 0) {
                 const double g = beta_over_tau * fma(cph, ore, sph * oim) - al * ud[c];
                 const size_t ui = ((size_t)im.b * a.K + j) * a.C + c;
@@ -578,24 +685,38 @@ constexpr Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-#define ISM_SP_DISPATCH(KERNEL, R, VI, GRID, BLOCK, SHMEM, ST, ARGS)                      \
-    switch (VI) {                                                                        \
-        case 0: hipLaunchKernelGGL((KERNEL<R, 1, 2, true>), GRID, BLOCK, SHMEM, ST, ARGS); break;  \
-        case 1: hipLaunchKernelGGL((KERNEL<R, 1, 2, false>), GRID, BLOCK, SHMEM, ST, ARGS); break; \
-        case 2: hipLaunchKernelGGL((KERNEL<R, 2, 2, false>), GRID, BLOCK, SHMEM, ST, ARGS); break; \
-        case 3: hipLaunchKernelGGL((KERNEL<R, 4, 1, false>), GRID, BLOCK, SHMEM, ST, ARGS); break; \
-        case 4: hipLaunchKernelGGL((KERNEL<R, 8, 1, false>), GRID, BLOCK, SHMEM, ST, ARGS); break; \
-        case 5: hipLaunchKernelGGL((KERNEL<R, 12, 1, false>), GRID, BLOCK, SHMEM, ST, ARGS); break;\
-        case 6: hipLaunchKernelGGL((KERNEL<R, 16, 1, false>), GRID, BLOCK, SHMEM, ST, ARGS); break;\
-        case 7: hipLaunchKernelGGL((KERNEL<R, 4, 4, false>), GRID, BLOCK, SHMEM, ST, ARGS); break; \
-        case 8: hipLaunchKernelGGL((KERNEL<R, 3, 8, false>), GRID, BLOCK, SHMEM, ST, ARGS); break; \
-        default: return hipErrorInvalidValue;                                            \
+#define ISM_SP_DISPATCH(KERNEL, R, X, VI, GRID, BLOCK, SHMEM, ST, ARGS)                            \
+    switch (VI) {                                                                                \
+        case 0: launch_with_shm(KERNEL<R, 1, 2, true, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break;  \
+        case 1: launch_with_shm(KERNEL<R, 1, 2, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break; \
+        case 2: launch_with_shm(KERNEL<R, 2, 2, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break; \
+        case 3: launch_with_shm(KERNEL<R, 4, 1, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break; \
+        case 4: launch_with_shm(KERNEL<R, 8, 1, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break; \
+        case 5: launch_with_shm(KERNEL<R, 12, 1, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break;\
+        case 6: launch_with_shm(KERNEL<R, 16, 1, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break;\
+        case 7: launch_with_shm(KERNEL<R, 4, 4, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break; \
+        case 8: launch_with_shm(KERNEL<R, 3, 8, false, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break; \
+        default: return hipErrorInvalidValue;                                                    \
     }
+
+template <typename Kern>
+static void launch_with_shm(Kern kf, dim3 grid, dim3 block, size_t shm, hipStream_t st,
+                            const SpArgs& a) {
+    if (shm > 65536)
+        hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(kf, grid, block, shm, st, a);
+}
+
+// LDS bytes of the block exchange: (4 + 2 CG) row slots of DP values
+static size_t sp_block_shmem(int vi, int dp, int precision) {
+    const int cg = kVariants[vi].CG;
+    return (size_t)(4 + 2 * cg) * dp * (precision == ISM_FP64 ? 8 : 4);
+}
 
 }  // namespace
 
 int sp_variant_index(int CG, int WC, int realh, int d) {
-    if (d < 1 || d > WAVE) return -1;
+    if (d < 1 || d > 256) return -1;
     int best = -1;
     long best_cost = 0;
     for (int i = 0; i < kNumVariants; ++i) {
@@ -620,26 +741,39 @@ hipError_t sp_launch_params(const SpArgs& a, const double* h0norm, const double*
     return hipGetLastError();
 }
 
-hipError_t sp_launch_assemble(const SpArgs& a, int vi, int precision, hipStream_t st) {
-    const long waves = (long)a.B * a.waves_per_inst;
-    const dim3 grid((unsigned)((waves + WPB - 1) / WPB)), block(WAVE * WPB);
-    if (precision == ISM_FP64) {
-        ISM_SP_DISPATCH(k_sp_assemble, double, vi, grid, block, 0, st, a);
+template <template <typename> class X>
+static hipError_t sp_launch_kernel(const SpArgs& a, int vi, int precision, hipStream_t st,
+                                   bool assemble) {
+    dim3 grid, block;
+    size_t shm = 0;
+    if (!X<float>::kBlock) {
+        const long waves = (long)a.B * a.waves_per_inst;
+        grid = dim3((unsigned)((waves + WPB - 1) / WPB));
+        block = dim3(WAVE * WPB);
     } else {
-        ISM_SP_DISPATCH(k_sp_assemble, float, vi, grid, block, 0, st, a);
+        const int dp = (a.d + WAVE - 1) / WAVE * WAVE;
+        grid = dim3((unsigned)a.items_per_inst, (unsigned)a.B);
+        block = dim3(dp);
+        shm = sp_block_shmem(vi, dp, precision);
+    }
+    if (assemble) {
+        if (precision == ISM_FP64) { ISM_SP_DISPATCH(k_sp_assemble, double, X, vi, grid, block, shm, st, a); }
+        else { ISM_SP_DISPATCH(k_sp_assemble, float, X, vi, grid, block, shm, st, a); }
+    } else {
+        if (precision == ISM_FP64) { ISM_SP_DISPATCH(k_sp_slice, double, X, vi, grid, block, shm, st, a); }
+        else { ISM_SP_DISPATCH(k_sp_slice, float, X, vi, grid, block, shm, st, a); }
     }
     return hipGetLastError();
 }
 
+hipError_t sp_launch_assemble(const SpArgs& a, int vi, int precision, hipStream_t st) {
+    return a.d <= WAVE ? sp_launch_kernel<XWave>(a, vi, precision, st, true)
+                       : sp_launch_kernel<XBlock>(a, vi, precision, st, true);
+}
+
 hipError_t sp_launch_slice(const SpArgs& a, int vi, int precision, hipStream_t st) {
-    const long waves = (long)a.B * a.waves_per_inst;
-    const dim3 grid((unsigned)((waves + WPB - 1) / WPB)), block(WAVE * WPB);
-    if (precision == ISM_FP64) {
-        ISM_SP_DISPATCH(k_sp_slice, double, vi, grid, block, 0, st, a);
-    } else {
-        ISM_SP_DISPATCH(k_sp_slice, float, vi, grid, block, 0, st, a);
-    }
-    return hipGetLastError();
+    return a.d <= WAVE ? sp_launch_kernel<XWave>(a, vi, precision, st, false)
+                       : sp_launch_kernel<XBlock>(a, vi, precision, st, false);
 }
 
 hipError_t sp_launch_boundary(const BndArgs& a, hipStream_t st) {

@@ -48,7 +48,24 @@ CASES = [
     ("spin2_K16_N16_NeqK", lambda: problems.spin2(K=16, N=16)),
     ("spin2_K25_N1", lambda: problems.spin2(K=25, N=1)),
     ("rotor_B3_K90_N7", lambda: problems.rotor(batch=3, K=90, N=7, T=0.5)),
+    ("rotor_j40_B2_K40_N6", lambda: problems.rotor(batch=2, jmax=40, K=40, N=6, T=0.1)),
+    ("chain4_state_K21_N4", lambda: _chain_random(11, n=4, T=0.4, K=21, N=4)),
+    ("chain7_state_K12_N3_block", lambda: _chain_random(12, n=7, T=0.3, K=12, N=3)),
+    ("chain8_state_K10_N4_block", lambda: _chain_random(13, n=8, T=0.3, K=10, N=4)),
 ]
+
+
+def _chain_random(seed, n, T, K, N):
+    """Spin-chain Hamiltonian with seeded random initial and target states: the transfer
+    |0..0> -> |1..1> at small controls has gradients of size ~(tau u)^n, far below the
+    rounding scale of the terms that form them, which makes relative errors meaningless."""
+    p = problems.spin_chain_state(seed, n=n, T=T, K=K, N=N)
+    rng = np.random.default_rng(seed + 100)
+    d = 2 ** n
+    for attr in ("psi0", "target"):
+        v = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+        setattr(p, attr, v / np.linalg.norm(v))
+    return p
 
 
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
@@ -202,6 +219,6 @@ def test_rotor_full_size_sampled():
         assert np.linalg.norm(psi32 - psiK) <= 1e-4
         assert _rel(g32, gr) <= 1e-3
     # every instance: unit norm of psi(T) and finite gradients
-    for prec in ("fp32", "fp64"):
-        assert np.all(np.abs(np.linalg.norm(res[prec][1], axis=1) - 1) <= 1e-5)
+    for prec, tol in (("fp32", 1e-4), ("fp64", tol64(p.K))):
+        assert np.all(np.abs(np.linalg.norm(res[prec][1], axis=1) - 1) <= tol)
         assert np.all(np.isfinite(res[prec][0]))
