@@ -205,6 +205,121 @@ const char* ism_status_string(int status);
 size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kind, int precision,
                              int gpe_grid);
 
+/*
+ * Serving: many independent solves on one device.
+ *
+ * A solve request is a problem (the arguments of ism_problem_create or
+ * ism_problem_create_gpe), initial controls and a stopping rule: run ISM iterations
+ * (ism_iterate semantics, u <- u + rho g) until F = |<psi(T)|psi_f>|^2 >= fid_stop or
+ * max_iter updates.  The server copies every input at submit time.  Requests are
+ * admitted in arrival order while the device memory they would hold
+ * (ism_problem_footprint, or the handle's actual bytes if larger) fits in hbm_budget;
+ * each admitted request gets its own handle and HIP stream, so the kernels of different
+ * requests overlap on the device.  Work is issued in chunks of iters_per_round
+ * iterations with no host synchronisation; ism_server_progress polls the chunks' events,
+ * retires finished requests (freeing their memory), admits waiting ones and issues the
+ * next chunks.  It never blocks on device work, except inside handle creation and when
+ * a finished request's controls are copied out.  A request's result does not depend on
+ * what else is being served: its kernels and their launch shapes are those of a solve
+ * run alone.
+ *
+ * A server is not thread-safe.  Time stamps are seconds on a monotonic clock
+ * (ism_server_clock).
+ */
+typedef struct ism_server ism_server;
+
+typedef enum ism_request_model {
+    ISM_REQ_FINITE = 0,     /* finite-dimensional state or gate problem (ism_problem_create) */
+    ISM_REQ_GPE = 1         /* Gross-Pitaevskii problem (ism_problem_create_gpe) */
+} ism_request_model;
+
+typedef struct ism_request {
+    int model;              /* ism_request_model */
+    int kind;               /* ism_kind (finite model) */
+    int precision;          /* ism_precision */
+    /* finite model: ism_problem_create arguments (d x d complex matrices, C of them in Hc) */
+    int d, n_ctrl;
+    const double* H0;
+    const double* Hc;
+    /* GPE model: ism_problem_create_gpe arguments */
+    int n_grid;
+    double L, g, V2;
+    const double* V0;
+    const double* V1;
+    /* both: psi0 and target (d, d x d or n_grid complex), time grid and partition */
+    const double* psi0;
+    const double* target;
+    double T;
+    int K, N;
+    const double* u0;       /* initial controls [K][C] (C = 1 for GPE) */
+    int max_iter;           /* >= 0 updates at most */
+    double rho;             /* gradient step (Eq. (gradStep), ascent) */
+    double fid_stop;        /* stop once F >= fid_stop (> 1 disables) */
+} ism_request;
+
+typedef enum ism_request_state {
+    ISM_REQ_QUEUED = 0,
+    ISM_REQ_RUNNING = 1,
+    ISM_REQ_DONE = 2,
+    ISM_REQ_FAILED = 3
+} ism_request_state;
+
+typedef struct ism_result {
+    int state;              /* ism_request_state */
+    int status;             /* ism_status of a failed request (ISM_OK otherwise) */
+    int iters;              /* updates performed so far */
+    double J, F;            /* at the current controls (valid once DONE) */
+    double t_arrival;       /* as passed to ism_server_submit */
+    double t_admit;         /* handle created (0 while queued) */
+    double t_done;          /* result available (0 before) */
+    size_t device_bytes;    /* memory charged against the budget */
+} ism_result;
+
+typedef struct ism_server_stats {
+    uint64_t submitted, completed, failed;
+    int queued, running;
+    size_t bytes_in_use, bytes_peak;
+    double busy_s;          /* time with at least one request running */
+} ism_server_stats;
+
+/* Monotonic clock in seconds, the time base of all server time stamps. */
+double ism_server_clock(void);
+
+/*
+ * Create a server on `device` with a device-memory budget of hbm_budget bytes for the
+ * admitted requests, iters_per_round iterations per issued chunk (>= 1) and at most
+ * max_running requests in flight at once (>= 1).  Errors: ISM_E_ARG, ISM_E_NOMEM,
+ * ISM_E_DEVICE.
+ */
+int ism_server_create(ism_server** out, int device, size_t hbm_budget, int iters_per_round,
+                      int max_running);
+
+/*
+ * Queue a request; its inputs are copied before return.  t_arrival < 0 stamps it with
+ * ism_server_clock().  *ticket receives its id.  ISM_E_ARG for missing or inconsistent
+ * fields, ISM_E_BUDGET if its footprint exceeds the whole budget (it could never be
+ * admitted).  Problems that are well-formed here but rejected by handle creation end
+ * in state ISM_REQ_FAILED with that status.
+ */
+int ism_server_submit(ism_server* s, const ism_request* req, double t_arrival, uint64_t* ticket);
+
+/* Poll the device, retire finished requests, admit and issue work (non-blocking, see
+ * above).  n_queued / n_running (nullable) receive the counts after the call. */
+int ism_server_progress(ism_server* s, int* n_queued, int* n_running);
+
+/* State of a request (ISM_E_ARG for an unknown ticket). */
+int ism_server_poll(ism_server* s, uint64_t ticket, ism_result* res);
+
+/* Take a finished (DONE or FAILED) request: *res as ism_server_poll, u_out (nullable)
+ * receives its final controls [K][C]; the server then forgets the ticket.
+ * ISM_E_STATE if the request is still queued or running. */
+int ism_server_take(ism_server* s, uint64_t ticket, ism_result* res, double* u_out);
+
+int ism_server_stats_get(ism_server* s, ism_server_stats* st);
+
+/* Wait for every running request's issued work, free everything (NULL-safe). */
+void ism_server_destroy(ism_server* s);
+
 #ifdef __cplusplus
 }
 #endif

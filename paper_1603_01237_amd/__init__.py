@@ -5,8 +5,8 @@ this package only marshals arguments to it (``_lib``), wraps its hand-written
 adjoint in a ``torch.autograd.Function`` (``autograd``) and runs a
 continuous-batching solve server on top of it (``serve``).
 """
-from ._lib import (FP32_MIXED, FP64, GATE, STATE, IsmError, Problem, footprint,  # noqa: F401
-                   from_problem, lib)
+from ._lib import (FP32_MIXED, FP64, GATE, STATE, IsmError, Problem, Server,  # noqa: F401
+                   footprint, from_problem, lib)
 
-__all__ = ["Problem", "IsmError", "from_problem", "footprint", "lib", "FP64", "FP32_MIXED",
-           "STATE", "GATE"]
+__all__ = ["Problem", "Server", "IsmError", "from_problem", "footprint", "lib", "FP64",
+           "FP32_MIXED", "STATE", "GATE"]

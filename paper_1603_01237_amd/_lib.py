@@ -24,7 +24,11 @@ EXPORTED = [
     "ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient",
     "ism_iterate", "ism_fidelity", "ism_problem_info", "ism_status_string", "ism_problem_footprint",
     "ism_set_timing", "ism_kernel_times",
+    "ism_server_clock", "ism_server_create", "ism_server_submit", "ism_server_progress",
+    "ism_server_poll", "ism_server_take", "ism_server_stats_get", "ism_server_destroy",
 ]
+REQ_FINITE, REQ_GPE = 0, 1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 
 
 class IsmError(RuntimeError):
@@ -49,6 +53,28 @@ class Info(ct.Structure):
 
 class KernelTime(ct.Structure):
     _fields_ = [("name", ct.c_char_p), ("launches", ct.c_int), ("total_ms", ct.c_double)]
+
+
+class Request(ct.Structure):
+    _fields_ = [("model", ct.c_int), ("kind", ct.c_int), ("precision", ct.c_int),
+                ("d", ct.c_int), ("n_ctrl", ct.c_int), ("H0", ct.c_void_p), ("Hc", ct.c_void_p),
+                ("n_grid", ct.c_int), ("L", ct.c_double), ("g", ct.c_double), ("V2", ct.c_double),
+                ("V0", ct.c_void_p), ("V1", ct.c_void_p), ("psi0", ct.c_void_p),
+                ("target", ct.c_void_p), ("T", ct.c_double), ("K", ct.c_int), ("N", ct.c_int),
+                ("u0", ct.c_void_p), ("max_iter", ct.c_int), ("rho", ct.c_double),
+                ("fid_stop", ct.c_double)]
+
+
+class Result(ct.Structure):
+    _fields_ = [("state", ct.c_int), ("status", ct.c_int), ("iters", ct.c_int),
+                ("J", ct.c_double), ("F", ct.c_double), ("t_arrival", ct.c_double),
+                ("t_admit", ct.c_double), ("t_done", ct.c_double), ("device_bytes", ct.c_size_t)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("failed", ct.c_uint64),
+                ("queued", ct.c_int), ("running", ct.c_int), ("bytes_in_use", ct.c_size_t),
+                ("bytes_peak", ct.c_size_t), ("busy_s", ct.c_double)]
 
 
 _lib = None
@@ -94,6 +120,20 @@ def lib():
     L.ism_kernel_times.restype = ct.c_int
     L.ism_problem_footprint.argtypes = [ct.c_int] * 7 + [ct.c_int]
     L.ism_problem_footprint.restype = ct.c_size_t
+    L.ism_server_clock.argtypes = []
+    L.ism_server_clock.restype = ct.c_double
+    L.ism_server_create.argtypes = [ct.POINTER(vp), ct.c_int, ct.c_size_t, ct.c_int, ct.c_int]
+    L.ism_server_submit.argtypes = [vp, ct.POINTER(Request), ct.c_double,
+                                    ct.POINTER(ct.c_uint64)]
+    L.ism_server_progress.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
+    L.ism_server_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(Result)]
+    L.ism_server_take.argtypes = [vp, ct.c_uint64, ct.POINTER(Result), vp]
+    L.ism_server_stats_get.argtypes = [vp, ct.POINTER(ServerStats)]
+    L.ism_server_destroy.argtypes = [vp]
+    L.ism_server_destroy.restype = None
+    for name in ("ism_server_create", "ism_server_submit", "ism_server_progress",
+                 "ism_server_poll", "ism_server_take", "ism_server_stats_get"):
+        getattr(L, name).restype = ct.c_int
     for name in ("ism_problem_create", "ism_problem_create_gpe", "ism_set_controls",
                  "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient", "ism_iterate",
                  "ism_fidelity", "ism_problem_info"):
@@ -317,3 +357,104 @@ def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=No
     if set_u:
         p.set_controls(prob.u0[:B])
     return p
+
+
+def _result_dict(r: Result) -> dict:
+    return {f: getattr(r, f) for f, _ in Result._fields_}
+
+
+class Server:
+    """libism serving loop (admission by device-memory budget, one handle and stream per
+    admitted request, chunked iterations, non-blocking completion polling)."""
+
+    def __init__(self, hbm_budget: int, iters_per_round: int = 10, max_running: int = 64,
+                 device: int = 0):
+        L = lib()
+        h = ct.c_void_p()
+        _check(L.ism_server_create(ct.byref(h), int(device), int(hbm_budget),
+                                   int(iters_per_round), int(max_running)), "ism_server_create")
+        self._h = h
+        self._meta = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(lib().ism_server_clock())
+
+    def submit(self, prob, max_iter: int, rho: float, fid_stop: float = 2.0,
+               precision="fp32", t_arrival: float = -1.0) -> int:
+        """Queue the solve of ``prob`` (a problems.FiniteProblem with batch 1, or a
+        problems.GpeProblem) from its u0; returns the ticket."""
+        r = Request()
+        keep = []
+
+        def ptr(a, dt):
+            a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+            keep.append(a)
+            return a.ctypes.data
+
+        r.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if hasattr(prob, "V0"):
+            r.model = REQ_GPE
+            r.n_grid, r.L, r.g, r.V2 = prob.n, prob.L, prob.g, prob.V2
+            r.V0, r.V1 = ptr(prob.V0, np.float64), ptr(prob.V1, np.float64)
+            C = 1
+        else:
+            if prob.H0.ndim == 3 and prob.H0.shape[0] != 1:
+                raise ValueError("a served request holds one instance")
+            r.model = REQ_FINITE
+            r.kind = GATE if prob.kind == "gate" else STATE
+            r.d, r.n_ctrl = prob.Hc.shape[-1], prob.Hc.shape[0]
+            r.H0 = ptr(prob.H0.reshape(r.d, r.d), np.complex128)
+            r.Hc = ptr(prob.Hc, np.complex128)
+            C = r.n_ctrl
+        r.psi0, r.target = ptr(prob.psi0, np.complex128), ptr(prob.target, np.complex128)
+        r.T, r.K, r.N = float(prob.T), int(prob.K), int(prob.N)
+        u0 = np.asarray(prob.u0, dtype=np.float64).reshape(-1, prob.K, C)[0]
+        r.u0 = ptr(u0, np.float64)
+        r.max_iter, r.rho, r.fid_stop = int(max_iter), float(rho), float(fid_stop)
+        t = ct.c_uint64(0)
+        _check(lib().ism_server_submit(self._h, ct.byref(r), float(t_arrival), ct.byref(t)),
+               "ism_server_submit")
+        self._meta[t.value] = (prob.K, C)
+        return t.value
+
+    def progress(self):
+        q, r = ct.c_int(0), ct.c_int(0)
+        _check(lib().ism_server_progress(self._h, ct.byref(q), ct.byref(r)), "ism_server_progress")
+        return q.value, r.value
+
+    def poll(self, ticket: int) -> dict:
+        r = Result()
+        _check(lib().ism_server_poll(self._h, ticket, ct.byref(r)), "ism_server_poll")
+        return _result_dict(r)
+
+    def take(self, ticket: int):
+        """(result dict, final controls (K, C) or None if the request failed)."""
+        K, C = self._meta[ticket]
+        u = np.empty((K, C), dtype=np.float64)
+        r = Result()
+        _check(lib().ism_server_take(self._h, ticket, ct.byref(r), _cptr(u)), "ism_server_take")
+        del self._meta[ticket]
+        return _result_dict(r), (u if r.state == REQ_DONE else None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ism_server_stats_get(self._h, ct.byref(st)), "ism_server_stats_get")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().ism_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -400,6 +400,31 @@ int copy_boundary_state(ism_problem* p, double* out, int which_end) {
     return copy_rows_out(p, out, base, e * sizeof(dcx), (size_t)(p->N + 1) * e * sizeof(dcx), p->B);
 }
 
+// Start of a served solve: every instance active, flags cleared, boundary pass at the
+// initial controls (J, F and the freeze decision for the first update).
+int serve_begin(ism_problem* p, double fid_stop) {
+    std::vector<int> ones(p->B, 1);
+    ISM_TRY_HIP(hipMemcpyAsync(p->active, ones.data(), p->B * sizeof(int), hipMemcpyHostToDevice,
+                               p->stream));
+    ISM_TRY_HIP(hipStreamSynchronize(p->stream));      // `ones` is pageable and goes out of scope
+    ISM_TRY_HIP(hipMemsetAsync(p->flags, 0, 4 * sizeof(int), p->stream));
+    return boundary_pass(p, nullptr, fid_stop, true);
+}
+
+// n more iterations, enqueued with no host synchronisation: each is the slice pass with
+// the update u += rho g (skipped by frozen instances) followed by the boundary pass at the
+// new controls, so after the chunk J and F belong to the current u.  flags[1] counts the
+// instances still active after each of the n boundary passes.
+int serve_chunk(ism_problem* p, int n, double rho, double fid_stop) {
+    int st;
+    ISM_TRY_HIP(hipMemsetAsync(p->flags, 0, 4 * sizeof(int), p->stream));
+    for (int k = 0; k < n; ++k) {
+        if ((st = slice_pass(p, 1, rho, nullptr, true))) return st;
+        if ((st = boundary_pass(p, nullptr, fid_stop, true))) return st;
+    }
+    return ISM_OK;
+}
+
 }  // namespace ism
 
 using namespace ism;

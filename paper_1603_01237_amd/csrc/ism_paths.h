@@ -15,6 +15,10 @@ int read_flags(ism_problem* p, int* host_flags);
 int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism_options* o);
 int validate_common(int d, int C, double T, int K, int N, const ism_options* o);
 
+// serving (ism_api.cpp): enqueue-only iteration steps, no host synchronisation
+int serve_begin(ism_problem* p, double fid_stop);
+int serve_chunk(ism_problem* p, int n, double rho, double fid_stop);
+
 // dense gate path (k_gate.hip)
 int gate_create(ism_problem* p, const double* H0, int h0_batched, const double* Hc,
                 const double* psi0, const double* target);

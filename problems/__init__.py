@@ -344,3 +344,22 @@ def serving_trace(seed: int = 1004, n_req: int = 2000, rate: float = 200.0):
         out.append({"id": i, "arrival": t, "type": typ, "size": size, "N": N, "K": K,
                     "seed": int(rng.integers(0, 2 ** 31))})
     return out
+
+
+# per-type settings of a served solve: final time, gradient step
+SERVE_RHO = {"spin": 0.5, "rotor": 1.0, "gpe": 0.1}
+
+
+def request_problem(req: dict):
+    """The problem of one serving-trace request (batch 1): spin d=4 is the two-spin
+    system, d >= 16 the open chain with log2(d) spins (|0..0> -> |1..1>), both with T=2;
+    rotors with T=10 and the j<=4 target; GPE with dt=1e-3 (T = K dt) and the x0=5
+    ground-state target."""
+    typ, size, K, N, seed = req["type"], req["size"], req["K"], req["N"], req["seed"]
+    if typ == "spin":
+        if size == 4:
+            return spin2(seed=seed, K=K, N=N, T=2.0)
+        return spin_chain_state(seed, n=int(round(math.log2(size))), T=2.0, K=K, N=N)
+    if typ == "rotor":
+        return rotor(seed=seed, batch=1, jmax=size, T=10.0, K=K, N=N)
+    return gpe(seed=seed, n=size, K=K, N=N)

@@ -112,3 +112,39 @@ def test_footprint_scales():
     assert a > b > 0
     assert _lib.footprint(21, 1, 100, 200, 1) == 0      # N > K
     assert _lib.footprint(256, 16, 2000, 64, 1, kind=_lib.GATE) > 0
+
+
+def test_server_rejects_invalid_arguments_without_device():
+    from paper_1603_01237_amd import _lib
+    L = _lib.lib()
+    h = ct.c_void_p()
+    assert L.ism_server_create(ct.byref(h), 0, 1 << 30, 0, 4) == _lib.ISM_E_ARG   # no iterations
+    assert L.ism_server_create(ct.byref(h), 0, 1 << 30, 5, 0) == _lib.ISM_E_ARG   # no slots
+    assert L.ism_server_create(ct.byref(h), 0, 0, 5, 4) == _lib.ISM_E_ARG         # no budget
+    assert L.ism_server_create(None, 0, 1 << 30, 5, 4) == _lib.ISM_E_ARG
+    t = ct.c_uint64()
+    assert L.ism_server_submit(None, None, -1.0, ct.byref(t)) == _lib.ISM_E_ARG
+    assert L.ism_server_progress(None, None, None) == _lib.ISM_E_ARG
+    r = _lib.Result()
+    assert L.ism_server_poll(None, 1, ct.byref(r)) == _lib.ISM_E_ARG
+    assert L.ism_server_take(None, 1, None, None) == _lib.ISM_E_ARG
+    L.ism_server_destroy(None)
+    c1 = L.ism_server_clock()
+    c2 = L.ism_server_clock()
+    assert c2 >= c1 > 0
+
+
+def test_request_problems_of_trace_are_well_formed():
+    trace = problems.serving_trace(n_req=60)
+    kinds = set()
+    for req in trace[:60]:
+        if req["type"] == "gpe" or (req["type"] == "spin" and req["size"] == 256):
+            continue                         # large set-up, covered on the GPU
+        p = problems.request_problem(req)
+        kinds.add(req["type"])
+        assert p.K == req["K"] and p.N == req["N"]
+        assert p.u0.shape[0] == 1 and p.u0.shape[1] == p.K
+    assert {"spin", "rotor"} <= kinds
+    arr = np.array([r["arrival"] for r in problems.serving_trace()])
+    assert np.all(np.diff(arr) > 0)
+    assert abs(len(arr) / arr[-1] - 200.0) < 20.0     # 2000 arrivals at a mean rate of 200/s
