@@ -4,13 +4,15 @@
 // Step map: Strang splitting (Eq. (OS)) with exact kinetic half steps in Fourier space,
 //   a_j = F^-1 Kh F psi_j,  b_j = e^{-i theta_j} a_j,  theta_j = tau (V(x,u_j) + g |a_j|^2),
 //   psi_{j+1} = F^-1 Kh F b_j,  Kh = e^{-i tau k^2/4}.
-// Consecutive kinetic half steps are fused: a_{j+1} = F^-1 Kh^2 F b_j, so a step costs one
-// forward and one inverse FFT; psi itself is formed only at slice boundaries.
+// Inside a slice consecutive kinetic half steps are fused, a_{j+1} = F^-1 Kh^2 F b_j, so a
+// step costs one forward and one inverse FFT; at a slice end psi_{j1} = F^-1 Kh F b is
+// formed and the next slice restarts from it with a half step, exactly as a slice kernel
+// that starts from the stored psi(t_n) does.
 //
 // Exact discrete adjoint (real inner product Re<.|.>), fused the same way:
 //   nu'_j = F^-1 conj(Kh) F nu_{j+1};  g_j = dx sum_m dV/du Im(conj(nu'_j) b_j);
 //   w = e^{+i theta_j} nu'_j;  mu_j = w + 2 tau g Im(conj(w) a_j) a_j;
-//   nu_j = F^-1 conj(Kh) F mu_j  (nu'_{j-1} = F^-1 conj(Kh)^2 F mu_j).
+//   nu_j = F^-1 conj(Kh) F mu_j  (inside a slice nu'_{j-1} = F^-1 conj(Kh)^2 F mu_j).
 //
 // ISM, BEC variant (Sec. 4.C): slice n starts from psi(t_n) on the forward trajectory and
 // its adjoint ends on nu(t_{n+1}) of the adjoint trajectory; both boundary sequences come
@@ -18,9 +20,16 @@
 // no slice propagator exists to assemble).  The slice gradient equals the plain gradient
 // on the slice (weight 1).
 //
-// FFT: radix-4 Stockham, natural order in and out, ping-pong buffers in LDS, one
-// butterfly per thread per pass (n/4 threads), twiddles from a table built in FP64.
-// The whole state stays in LDS for the entire sweep.
+// Data layout: a workgroup of n/16 threads holds the state in registers, thread t owning
+// the points t + (n/16) i, i = 0..15.  The FFT is a Stockham transform of radices
+// 16, 16, 16 (n = 4096) or 16, 16, 4 (n = 1024): the first pass reads its inputs from
+// registers and the last pass leaves its outputs in registers in the same ownership
+// pattern, so the pointwise potential phase, the kinetic factors, the trajectory and the
+// gradient terms are formed in registers and only two exchanges per transform go through
+// one in-place LDS buffer (padded by one element per 16, which makes every access
+// pattern of the three passes bank-conflict free).  Butterflies, twiddles and the LDS
+// state are FP64 in both precisions; the FP32 mixed path stores the trajectory a_j and
+// forms the phase e^{-i theta} in FP32.
 #include <math.h>
 
 #include <algorithm>
@@ -32,70 +41,153 @@ namespace ism {
 namespace {
 
 template <typename R> struct Cx { R re, im; };
+using Cd = Cx<double>;
+
+__device__ __forceinline__ Cd cmul(Cd a, Cd b) {
+    return Cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ Cd cmulc(Cd a, Cd b) {      // a * conj(b)
+    return Cd{a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// multiplication by a forward root (SIGN = -1) or by its conjugate (SIGN = +1)
+template <int SIGN>
+__device__ __forceinline__ Cd cmul_s(Cd a, Cd w) { return SIGN < 0 ? cmul(a, w) : cmulc(a, w); }
 
 template <typename R>
-__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
-    return Cx<R>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
+__device__ __forceinline__ Cd up(Cx<R> v) { return Cd{(double)v.re, (double)v.im}; }
 template <typename R>
-__device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b) {    // a * conj(b)
-    return Cx<R>{a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
-}
+__device__ __forceinline__ Cx<R> down(Cd v) { return Cx<R>{(R)v.re, (R)v.im}; }
 
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 
-// Radix-4 Stockham FFT of n points held in LDS buffer `a` (scratch `b`), n/4 threads.
-// SIGN = -1: forward e^{-2 pi i jk/n}; SIGN = +1: inverse without the 1/n factor.
-// Returns the buffer holding the result.
-template <typename R>
-__device__ __forceinline__ Cx<double> up(Cx<R> v) {
-    return Cx<double>{(double)v.re, (double)v.im};
-}
-template <typename R>
-__device__ __forceinline__ Cx<R> down(Cx<double> v) {
-    return Cx<R>{(R)v.re, (R)v.im};
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// 4-point DFT in place, roots e^{SIGN 2 pi i/4}
+template <int SIGN>
+__device__ __forceinline__ void dft4(Cd& a, Cd& b, Cd& c, Cd& d) {
+    const Cd t0{a.re + c.re, a.im + c.im}, t1{a.re - c.re, a.im - c.im};
+    const Cd t2{b.re + d.re, b.im + d.im};
+    const Cd bd{b.re - d.re, b.im - d.im};
+    const Cd t3 = SIGN < 0 ? Cd{bd.im, -bd.re} : Cd{-bd.im, bd.re};     // (b - d) * SIGN i
+    a = Cd{t0.re + t2.re, t0.im + t2.im};
+    b = Cd{t1.re + t3.re, t1.im + t3.im};
+    c = Cd{t0.re - t2.re, t0.im - t2.im};
+    d = Cd{t1.re - t3.re, t1.im - t3.im};
 }
 
-// The butterflies run in FP64 with FP64 twiddles whatever the storage precision R: with
-// FP32-rounded twiddles every transform is non-unitary in the same way at every step and
-// the error grows linearly over a sweep; rounding only the stored values keeps it a random
-// walk.
-template <typename R, int SIGN>
-__device__ Cx<R>* fft_lds(Cx<R>* a, Cx<R>* b, const Cx<double>* __restrict__ tw, int n) {
-    const int j = threadIdx.x, q = n >> 2;
-    for (int Ns = 1; Ns < n; Ns <<= 2) {
-        Cx<double> v0 = up(a[j]), v1 = up(a[j + q]), v2 = up(a[j + 2 * q]), v3 = up(a[j + 3 * q]);
-        const int k = j & (Ns - 1);
-        const int stride = n / (4 * Ns);
-        if (Ns > 1) {
-            Cx<double> w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
-            if (SIGN > 0) {
-                w1.im = -w1.im;
-                w2.im = -w2.im;
-                w3.im = -w3.im;
-            }
-            v1 = cmul(v1, w1);
-            v2 = cmul(v2, w2);
-            v3 = cmul(v3, w3);
-        }
-        const Cx<double> a0{v0.re + v2.re, v0.im + v2.im}, a1{v0.re - v2.re, v0.im - v2.im};
-        const Cx<double> a2{v1.re + v3.re, v1.im + v3.im};
-        // (v1 - v3) times -i (forward) or +i (inverse)
-        const Cx<double> a3 = SIGN < 0 ? Cx<double>{v1.im - v3.im, -(v1.re - v3.re)}
-                                       : Cx<double>{-(v1.im - v3.im), v1.re - v3.re};
-        const int idx = (j / Ns) * Ns * 4 + k;
-        __syncthreads();                      // every thread has read a[]
-        b[idx] = down<R>(Cx<double>{a0.re + a2.re, a0.im + a2.im});
-        b[idx + Ns] = down<R>(Cx<double>{a1.re + a3.re, a1.im + a3.im});
-        b[idx + 2 * Ns] = down<R>(Cx<double>{a0.re - a2.re, a0.im - a2.im});
-        b[idx + 3 * Ns] = down<R>(Cx<double>{a1.re - a3.re, a1.im - a3.im});
-        __syncthreads();
-        Cx<R>* t = a;
-        a = b;
-        b = t;
+// cos and sin of 2 pi m / 16, m = 0..4
+__device__ constexpr double kC16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                       0.38268343236508977173, 0.0};
+
+// e^{SIGN 2 pi i m/16} for m = 0..9
+template <int SIGN>
+__device__ __forceinline__ Cd root16(int m) {
+    // reduce to the first quadrant: m = 4 q + r
+    const int q = m >> 2, r = m & 3;
+    double c = kC16[r], s = kC16[4 - r];
+    for (int k = 0; k < q; ++k) {      // multiply by i
+        const double t = c;
+        c = -s;
+        s = t;
     }
-    return a;
+    return Cd{c, SIGN * s};
+}
+
+// 16-point DFT in place (x[c] <- sum_r x[r] e^{SIGN 2 pi i r c/16}) as 4 x 4.
+template <int SIGN>
+__device__ __forceinline__ void dft16(Cd (&x)[16]) {
+#pragma unroll
+    for (int r1 = 0; r1 < 4; ++r1) dft4<SIGN>(x[r1], x[r1 + 4], x[r1 + 8], x[r1 + 12]);
+#pragma unroll
+    for (int r1 = 1; r1 < 4; ++r1)
+#pragma unroll
+        for (int c2 = 1; c2 < 4; ++c2) x[r1 + 4 * c2] = cmul(x[r1 + 4 * c2], root16<SIGN>(r1 * c2));
+    Cd y[16];
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+        Cd p = x[4 * c2], q = x[4 * c2 + 1], r = x[4 * c2 + 2], s = x[4 * c2 + 3];
+        dft4<SIGN>(p, q, r, s);
+        y[c2] = p;
+        y[c2 + 4] = q;
+        y[c2 + 8] = r;
+        y[c2 + 12] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = y[i];
+}
+
+// LDS carve-up of a workgroup
+struct Lds {
+    Cd* st;            // n + n/16: padded FFT exchange buffer
+    Cd* kf;            // n: e^{-i tau k^2/2} / n
+    Cd* tab;           // 768: [0,256) W_256^{r k}; [256,512) W_n^{16 r k}; [512,768) W_n^{r k}
+    double* red;       // 16
+};
+
+template <int NN>
+__device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
+    Lds L;
+    L.st = reinterpret_cast<Cd*>(raw);
+    L.kf = L.st + NN + NN / 16;
+    L.tab = L.kf + NN;
+    L.red = reinterpret_cast<double*>(L.tab + 768);
+    return L;
+}
+
+// FFT of the register-resident state (natural order, thread t owns t + (NN/16) i), result
+// in the same layout.  SIGN = -1 forward e^{-2 pi i jk/n}; +1 inverse without 1/n.
+template <int NN, int SIGN>
+__device__ void fft(Cd (&x)[16], const Lds& L) {
+    constexpr int T = NN / 16;
+    const int t = threadIdx.x;
+    // pass 1: radix 16, sub-transform size 1 (no twiddles)
+    dft16<SIGN>(x);
+    __syncthreads();                          // earlier readers of st are done
+#pragma unroll
+    for (int c = 0; c < 16; ++c) L.st[pad(16 * t + c)] = x[c];
+    __syncthreads();
+    // pass 2: radix 16, sub-transform size 16
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = L.st[pad(t + T * r)];
+    const int k = t & 15;
+#pragma unroll
+    for (int r = 1; r < 16; ++r) x[r] = cmul_s<SIGN>(x[r], L.tab[r * 16 + k]);
+    dft16<SIGN>(x);
+    __syncthreads();                          // every thread has read its inputs
+    const int base = (t >> 4) * 256 + k;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) L.st[pad(base + 16 * c)] = x[c];
+    __syncthreads();
+    // pass 3: sub-transform size 256; twiddle W_n^{r k} = W_n^{16 r (k>>4)} W_n^{r (k&15)}
+    if constexpr (NN == 4096) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = L.st[pad(t + 256 * r)];
+        const int kh = t >> 4, kl = t & 15;
+#pragma unroll
+        for (int r = 1; r < 16; ++r)
+            x[r] = cmul_s<SIGN>(x[r], cmul(L.tab[256 + r * 16 + kh], L.tab[512 + r * 16 + kl]));
+        dft16<SIGN>(x);
+    } else {
+        static_assert(NN == 1024, "grid sizes 1024 and 4096");
+        Cd y[16];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int j = t + 64 * s, kh = j >> 4, kl = j & 15;
+            Cd v0 = L.st[pad(j)], v1 = L.st[pad(j + 256)], v2 = L.st[pad(j + 512)],
+               v3 = L.st[pad(j + 768)];
+            v1 = cmul_s<SIGN>(v1, cmul(L.tab[256 + 16 + kh], L.tab[512 + 16 + kl]));
+            v2 = cmul_s<SIGN>(v2, cmul(L.tab[256 + 32 + kh], L.tab[512 + 32 + kl]));
+            v3 = cmul_s<SIGN>(v3, cmul(L.tab[256 + 48 + kh], L.tab[512 + 48 + kl]));
+            dft4<SIGN>(v0, v1, v2, v3);
+            y[s] = v0;
+            y[s + 4] = v1;
+            y[s + 8] = v2;
+            y[s + 12] = v3;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) x[i] = y[i];
+    }
 }
 
 struct GpeArgs {
@@ -105,11 +197,10 @@ struct GpeArgs {
     const double* V0;
     const double* V1;
     double V2;
-    const void* tw;        // n twiddles e^{-2 pi i t/n} (FP64)
-    const void* Kh;        // n: e^{-i tau k^2/4} / n (FP64)
-    const void* Kf;        // n: e^{-i tau k^2/2} / n (FP64)
+    const dcx* tab;        // 768 FFT twiddles (FP64), layout of Lds::tab
+    const dcx* Kh;         // n: e^{-i tau k^2/4} / n (FP64)
+    const dcx* Kf;         // n: e^{-i tau k^2/2} / n (FP64)
     double* u;             // B*K
-    const double* alpha;   // unused by the model (alpha = 0 in Sec. 4.C), kept for uniformity
     dcx* Psi;              // B*(N+1)*n  psi(t_n)
     dcx* Lam;              // B*(N+1)*n  nu(t_n)
     const dcx* psi0;       // n
@@ -126,160 +217,136 @@ struct GpeArgs {
     int update;
 };
 
-template <typename R>
-__device__ __forceinline__ double block_sum(double v, double* red) {
-    // wave reduction, then across wavefronts (deterministic order)
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+// tables into LDS, potentials into registers
+template <int NN>
+__device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, double (&v0)[16],
+                                      double (&v1)[16]) {
+    constexpr int T = NN / 16;
+    const int t = threadIdx.x;
+    for (int i = t; i < NN; i += T) L.kf[i] = Cd{A.Kf[i].re, A.Kf[i].im};
+    for (int i = t; i < 768; i += T) L.tab[i] = Cd{A.tab[i].re, A.tab[i].im};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v0[i] = A.V0[t + T * i];
+        v1[i] = A.V1[t + T * i];
+    }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = v;
+}
+
+// deterministic workgroup sum (wave tree, then the wavefront partials in order)
+template <int NN>
+__device__ __forceinline__ double block_sum(double v, const Lds& L) {
+    constexpr int NW = NN / 16 / 64;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if constexpr (NW == 1) return v;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    for (int i = 0; i < nw; ++i) s += red[i];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) s += L.red[i];
     return s;
 }
 
-// theta_j and b_j = e^{-i theta} a_j for this thread's four points; V formed in FP64.
-template <typename R>
-__device__ __forceinline__ void potential_phase(const GpeArgs& A, const double (&v0)[4],
-                                                const double (&v1)[4], double u,
-                                                const Cx<double> (&a)[4], Cx<R> (&e)[4]) {
+// x <- F^-1 diag(k) F x with k read at the owned frequencies from LDS or global memory;
+// CONJ uses conj(k) (adjoint kicks)
+template <int NN, bool CONJ>
+__device__ __forceinline__ void kick(Cd (&x)[16], const Lds& L, const Cd* kt) {
+    constexpr int T = NN / 16;
+    fft<NN, -1>(x, L);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double V = v0[r] + u * v1[r] + u * u * A.V2;
-        const R th = (R)(A.tau * (V + A.g * (a[r].re * a[r].re + a[r].im * a[r].im)));
-        R sn, cs;
-        sincos_r(th, &sn, &cs);
-        e[r] = Cx<R>{cs, -sn};   // e^{-i theta}
+    for (int i = 0; i < 16; ++i) {
+        const Cd k = kt[threadIdx.x + T * i];
+        x[i] = CONJ ? cmulc(x[i], k) : cmul(x[i], k);
+    }
+    fft<NN, 1>(x, L);
+}
+
+template <int NN>
+__device__ __forceinline__ void load_state(Cd (&x)[16], const dcx* src) {
+    constexpr int T = NN / 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const dcx v = src[threadIdx.x + T * i];
+        x[i] = Cd{v.re, v.im};
     }
 }
 
-// Forward steps j = j0 .. j1-1 starting from a_{j0} held in buf (LDS, natural order).
-// Stores a_j in traj; if psi_out is given, psi_{j1} = F^-1 Kh F b_{j1-1} is written there.
-// On return buf holds a_{j1} (if want_next) — used by the sequential sweep.
+template <int NN>
+__device__ __forceinline__ void store_state(dcx* dst, const Cd (&x)[16]) {
+    constexpr int T = NN / 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[threadIdx.x + T * i] = dcx{x[i].re, x[i].im};
+}
+
+// e^{-i theta} at the owned points, theta = tau (V(x,u) + g |a|^2) (V in FP64)
 template <typename R>
-__device__ Cx<double>* forward_steps(const GpeArgs& A, int b, int j0, int j1, Cx<double>* buf,
-                                     Cx<double>* scr,
-                                const double (&v0)[4], const double (&v1)[4], Cx<R>* traj_b,
-                                dcx* psi_out, bool want_next) {
-    const int n = A.n, q = n >> 2, t = threadIdx.x;
-    const Cx<double>* tw = reinterpret_cast<const Cx<double>*>(A.tw);
-    const Cx<double>* Kh = reinterpret_cast<const Cx<double>*>(A.Kh);
-    const Cx<double>* Kf = reinterpret_cast<const Cx<double>*>(A.Kf);
+__device__ __forceinline__ Cd phase(const GpeArgs& A, double v0, double v1, double u, Cd a) {
+    const double V = v0 + u * v1 + u * u * A.V2;
+    const R th = (R)(A.tau * (V + A.g * (a.re * a.re + a.im * a.im)));
+    R sn, cs;
+    sincos_r(th, &sn, &cs);
+    return Cd{(double)cs, -(double)sn};
+}
+
+// Forward steps j0 .. j1-1 from x = a_{j0}, storing a_j in traj_b.  After the last step:
+// psi_{j1} = F^-1 Kh F b_{j1-1} is formed (and written to psi_out if given) when psi_out or
+// cont is set, and with cont x = a_{j1} = F^-1 Kh F psi_{j1} on return.
+template <int NN, typename R>
+__device__ void fwd_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, Cd (&x)[16],
+                        const double (&v0)[16], const double (&v1)[16], Cx<R>* traj_b,
+                        dcx* psi_out, bool cont) {
+    constexpr int T = NN / 16;
+    const int t = threadIdx.x;
     for (int j = j0; j < j1; ++j) {
-        Cx<double> a[4];
-        Cx<R> e[4];
+        Cx<R>* tj = traj_b + (size_t)j * NN;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = buf[t + r * q];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) traj_b[(size_t)j * n + t + r * q] = down<R>(a[r]);
-        if (j == j1 - 1 && !psi_out && !want_next) return buf;   // trajectory complete
+        for (int i = 0; i < 16; ++i) tj[t + T * i] = down<R>(x[i]);
+        const bool last = j == j1 - 1;
+        if (last && !psi_out && !cont) return;
         const double u = A.u[(size_t)b * A.K + j];
-        potential_phase<R>(A, v0, v1, u, a, e);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) buf[t + r * q] = cmul(a[r], up(e[r]));   // b_j
-        __syncthreads();
-        Cx<double>* fb = fft_lds<double, -1>(buf, scr, tw, n);                      // F b_j
-        Cx<double>* other = fb == buf ? scr : buf;
-        const bool last = (j == j1 - 1);
-        if (last && psi_out) {
-            // psi_{j1} = F^-1 Kh F b_j into `other`, then back to fb's data for a_{j+1}
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = t + r * q;
-                other[m] = cmul(fb[m], Kh[m]);
-            }
-            __syncthreads();
-            // keep F b_j: transform a copy
-            Cx<double> keep[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) keep[r] = fb[t + r * q];
-            __syncthreads();
-            Cx<double>* pr = fft_lds<double, 1>(other, fb, tw, n);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = t + r * q;
-                psi_out[m] = dcx{(double)pr[m].re, (double)pr[m].im};
-            }
-            __syncthreads();
-            if (!want_next) return pr;
-            Cx<double>* dst = pr == buf ? scr : buf;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dst[t + r * q] = keep[r];
-            __syncthreads();
-            fb = dst;
-            other = dst == buf ? scr : buf;
-        } else if (last && !want_next) {
-            return fb;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = t + r * q;
-            fb[m] = cmul(fb[m], Kf[m]);
-        }
-        __syncthreads();
-        Cx<double>* an = fft_lds<double, 1>(fb, other, tw, n);                      // a_{j+1}
-        if (an != buf) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = t + r * q;
-                const Cx<double> v = an[m];
-                __syncthreads();
-                buf[m] = v;
-            }
-            __syncthreads();
+        for (int i = 0; i < 16; ++i) x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, x[i]));
+        if (!last) {
+            kick<NN, false>(x, L, L.kf);
+        } else {
+            kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
+            if (psi_out) store_state<NN>(psi_out, x);
+            if (cont) kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
         }
     }
-    return buf;
 }
 
-// nu'_{j} from nu_{j+1} held in buf:  F^-1 conj(Kh) F nu
-template <typename R>
-__device__ Cx<double>* adj_half_kick(const GpeArgs& A, Cx<double>* buf, Cx<double>* scr, bool full) {
-    const int n = A.n, q = n >> 2, t = threadIdx.x;
-    const Cx<double>* tw = reinterpret_cast<const Cx<double>*>(A.tw);
-    const Cx<double>* Kt = reinterpret_cast<const Cx<double>*>(full ? A.Kf : A.Kh);
-    Cx<double>* f = fft_lds<double, -1>(buf, scr, tw, n);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int m = t + r * q;
-        f[m] = cmulc(f[m], Kt[m]);
-    }
-    __syncthreads();
-    Cx<double>* o = f == buf ? scr : buf;
-    return fft_lds<double, 1>(f, o, tw, n);
-}
-
-// Adjoint steps j = j1-1 down to j0, starting from nu'_{j1-1} in buf; a_j read from traj.
-// Every step but the last continues with the fused kick (nu'_{j-1} in buf); after the last
-// step final_kick selects: 0 nothing, 1 the half kick nu_{j0} (written to nu_out),
-// 2 the fused kick nu'_{j0-1}.  Computes the gradient of each step if grad_on.
-template <typename R>
-__device__ void adjoint_steps(const GpeArgs& A, int b, int j0, int j1, Cx<double>* buf,
-                              Cx<double>* scr,
-                              const double (&v0)[4], const double (&v1)[4], const Cx<R>* traj_b,
-                              dcx* nu_out, int final_kick, bool grad_on, bool upd, double* red) {
-    const int n = A.n, q = n >> 2, t = threadIdx.x;
+// Adjoint steps j1-1 down to j0 from x = nu'_{j1-1}, reading a_j from traj_b.  After step
+// j0 (mu_{j0} in x): final 0 stops; 1 forms nu_{j0} (written to nu_out); 2 forms nu_{j0},
+// writes it, and continues to x = nu'_{j0-1}.  With grad_on every step's gradient is formed
+// and, with upd, the update u_j += rho g_j applied (u_j is not read again here).
+template <int NN, typename R>
+__device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, Cd (&x)[16],
+                        const double (&v0)[16], const double (&v1)[16], const Cx<R>* traj_b,
+                        dcx* nu_out, int final_kick, bool grad_on, bool upd) {
+    constexpr int T = NN / 16;
+    const int t = threadIdx.x;
+    const Cd* conjKh = reinterpret_cast<const Cd*>(A.Kh);
     for (int j = j1 - 1; j >= j0; --j) {
-        Cx<double> a[4], nup[4];
-        Cx<R> e[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            a[r] = up(traj_b[(size_t)j * n + t + r * q]);
-            nup[r] = buf[t + r * q];
-        }
+        const Cx<R>* tj = traj_b + (size_t)j * NN;
         const double u = A.u[(size_t)b * A.K + j];
-        potential_phase<R>(A, v0, v1, u, a, e);
-        if (grad_on) {
-            double part = 0.0;
+        double part = 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const Cx<double> bb = cmul(a[r], up(e[r]));
-                const double dV = v1[r] + 2.0 * u * A.V2;
-                // Im(conj(nu') b)
-                part += dV * ((double)nup[r].re * (double)bb.im - (double)nup[r].im * (double)bb.re);
+        for (int i = 0; i < 16; ++i) {
+            const Cd a = up<R>(tj[t + T * i]);
+            const Cd e = phase<R>(A, v0[i], v1[i], u, a);
+            if (grad_on) {
+                const Cd bb = cmul(a, e);
+                const double dV = v1[i] + 2.0 * u * A.V2;
+                part += dV * (x[i].re * bb.im - x[i].im * bb.re);      // Im(conj(nu') b)
             }
-            const double gj = A.dx * block_sum<R>(part, red);
+            const Cd w = cmulc(x[i], e);                               // e^{+i theta} nu'
+            const double f = 2.0 * A.tau * A.g * (w.re * a.im - w.im * a.re);
+            x[i] = Cd{w.re + f * a.re, w.im + f * a.im};
+        }
+        if (grad_on) {
+            const double gj = A.dx * block_sum<NN>(part, L);
             if (t == 0) {
                 const size_t ui = (size_t)b * A.K + j;
                 if (A.grad) A.grad[ui] = gj;
@@ -287,114 +354,46 @@ __device__ void adjoint_steps(const GpeArgs& A, int b, int j0, int j1, Cx<double
                 if (!(fabs(gj) < 1e300)) atomicOr(&A.flags[0], 1);
             }
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            // w = e^{+i theta} nu' = nu' * conj(e);  mu = w + 2 tau g Im(conj(w) a) a
-            const Cx<double> w = cmulc(nup[r], up(e[r]));
-            const Cx<double> ad = a[r];
-            const double f = 2.0 * A.tau * A.g * (w.re * ad.im - w.im * ad.re);
-            buf[t + r * q] = Cx<double>{w.re + f * ad.re, w.im + f * ad.im};
+        if (j > j0) {
+            kick<NN, true>(x, L, L.kf);
+        } else if (final_kick > 0) {
+            kick<NN, true>(x, L, conjKh);
+            if (nu_out) store_state<NN>(nu_out, x);
+            if (final_kick == 2) kick<NN, true>(x, L, conjKh);
         }
-        __syncthreads();
-        const bool last = (j == j0);
-        if (last && final_kick == 0) break;
-        Cx<double>* res = adj_half_kick<R>(A, buf, scr, !(last && final_kick == 1));
-        if (last && nu_out && final_kick == 1) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = t + r * q;
-                nu_out[m] = dcx{(double)res[m].re, (double)res[m].im};
-            }
-        }
-        if (res != buf) {
-            Cx<double> v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = res[t + r * q];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < 4; ++r) buf[t + r * q] = v[r];
-        }
-        __syncthreads();
     }
-}
-
-template <typename R>
-__device__ __forceinline__ void load_pot(const GpeArgs& A, double (&v0)[4], double (&v1)[4]) {
-    const int q = A.n >> 2;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        v0[r] = A.V0[threadIdx.x + r * q];
-        v1[r] = A.V1[threadIdx.x + r * q];
-    }
-}
-
-// a_{j0} = F^-1 Kh F psi with psi (FP64) read from src
-template <typename R>
-__device__ Cx<double>* first_half_kick(const GpeArgs& A, const dcx* src, Cx<double>* buf,
-                                       Cx<double>* scr) {
-    const int n = A.n, q = n >> 2, t = threadIdx.x;
-    const Cx<double>* tw = reinterpret_cast<const Cx<double>*>(A.tw);
-    const Cx<double>* Kh = reinterpret_cast<const Cx<double>*>(A.Kh);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const dcx v = src[t + r * q];
-        buf[t + r * q] = Cx<double>{v.re, v.im};
-    }
-    __syncthreads();
-    Cx<double>* f = fft_lds<double, -1>(buf, scr, tw, n);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int m = t + r * q;
-        f[m] = cmul(f[m], Kh[m]);
-    }
-    __syncthreads();
-    Cx<double>* o = f == buf ? scr : buf;
-    Cx<double>* res = fft_lds<double, 1>(f, o, tw, n);
-    if (res != buf) {
-        Cx<double> v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = res[t + r * q];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) buf[t + r * q] = v[r];
-        __syncthreads();
-    }
-    return buf;
 }
 
 // Sequential forward sweep of one instance: psi(t_n) for every n, a_j for every step,
 // J and F at T.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_gpe_fwd_sweep(GpeArgs A) {
+template <int NN, typename R>
+__global__ __launch_bounds__(NN / 16) void k_gpe_fwd_sweep(GpeArgs A) {
     extern __shared__ unsigned char smem_raw[];
-    Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem_raw);
-    Cx<double>* scr = buf + A.n;
-    double* red = reinterpret_cast<double*>(scr + A.n);
-    const int b = blockIdx.x, n = A.n, q = n >> 2, t = threadIdx.x;
-    double v0[4], v1[4];
-    load_pot<R>(A, v0, v1);
-    dcx* Psi_b = A.Psi + (size_t)b * (A.N + 1) * n;
-    Cx<R>* traj_b = reinterpret_cast<Cx<R>*>(A.traj) + (size_t)b * A.K * n;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Psi_b[t + r * q] = A.psi0[t + r * q];
-    first_half_kick<R>(A, A.psi0, buf, scr);
-    for (int nn = 0; nn < A.N; ++nn) {
-        forward_steps<R>(A, b, A.s[nn], A.s[nn + 1], buf, scr, v0, v1, traj_b,
-                         Psi_b + (size_t)(nn + 1) * n, nn + 1 < A.N);
-        __syncthreads();
-    }
-    // J = Re <psi_K|psi_f> dx, F = |<psi_K|psi_f> dx|^2
-    const dcx* pK = Psi_b + (size_t)A.N * n;
+    const Lds L = lds_carve<NN>(smem_raw);
+    const int b = blockIdx.x;
+    double v0[16], v1[16];
+    setup<NN>(A, L, v0, v1);
+    dcx* Psi_b = A.Psi + (size_t)b * (A.N + 1) * NN;
+    Cx<R>* traj_b = reinterpret_cast<Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
+    Cd x[16];
+    load_state<NN>(x, A.psi0);
+    store_state<NN>(Psi_b, x);
+    kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));      // a_0
+    for (int nn = 0; nn < A.N; ++nn)
+        fwd_run<NN, R>(A, L, b, A.s[nn], A.s[nn + 1], x, v0, v1, traj_b,
+                       Psi_b + (size_t)(nn + 1) * NN, nn + 1 < A.N);
+    // x = psi_K:  J = Re <psi_K|psi_f> dx,  F = |<psi_K|psi_f> dx|^2
+    constexpr int T = NN / 16;
     double zr = 0.0, zi = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const dcx p = pK[t + r * q], f = A.target[t + r * q];
-        zr += p.re * f.re + p.im * f.im;
-        zi += p.re * f.im - p.im * f.re;
+    for (int i = 0; i < 16; ++i) {
+        const dcx f = A.target[threadIdx.x + T * i];
+        zr += x[i].re * f.re + x[i].im * f.im;
+        zi += x[i].re * f.im - x[i].im * f.re;
     }
-    zr = A.dx * block_sum<R>(zr, red);
-    zi = A.dx * block_sum<R>(zi, red);
-    if (t == 0) {
+    zr = A.dx * block_sum<NN>(zr, L);
+    zi = A.dx * block_sum<NN>(zi, L);
+    if (threadIdx.x == 0) {
         const double F = zr * zr + zi * zi;
         A.J[b] = zr;
         A.F[b] = F;
@@ -408,116 +407,44 @@ __global__ __launch_bounds__(1024) void k_gpe_fwd_sweep(GpeArgs A) {
 }
 
 // Sequential adjoint sweep of one instance: nu(t_n) for every n.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_gpe_adj_sweep(GpeArgs A) {
+template <int NN, typename R>
+__global__ __launch_bounds__(NN / 16) void k_gpe_adj_sweep(GpeArgs A) {
     extern __shared__ unsigned char smem_raw[];
-    Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem_raw);
-    Cx<double>* scr = buf + A.n;
-    double* red = reinterpret_cast<double*>(scr + A.n);
-    const int b = blockIdx.x, n = A.n, q = n >> 2, t = threadIdx.x;
-    double v0[4], v1[4];
-    load_pot<R>(A, v0, v1);
-    dcx* Lam_b = A.Lam + (size_t)b * (A.N + 1) * n;
-    const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * n;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const dcx v = A.target[t + r * q];
-        Lam_b[(size_t)A.N * n + t + r * q] = v;
-        buf[t + r * q] = Cx<double>{v.re, v.im};
-    }
-    __syncthreads();
-    Cx<double>* res = adj_half_kick<R>(A, buf, scr, false);         // nu'_{K-1}
-    if (res != buf) {
-        Cx<double> v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = res[t + r * q];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) buf[t + r * q] = v[r];
-        __syncthreads();
-    }
-    for (int nn = A.N - 1; nn >= 0; --nn) {
-        // steps of slice nn; at its first step nu_{s_nn} is stored and nu'_{s_nn - 1} kept
-        const int j0 = A.s[nn], j1 = A.s[nn + 1];
-        adjoint_steps<R>(A, b, j0 + 1, j1, buf, scr, v0, v1, traj_b, nullptr, 2, false, false, red);
-        // step j0: store nu_{j0}, continue with nu'_{j0-1}
-        Cx<double> a[4], nup[4];
-        Cx<R> e[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            a[r] = up(traj_b[(size_t)j0 * n + t + r * q]);
-            nup[r] = buf[t + r * q];
-        }
-        potential_phase<R>(A, v0, v1, A.u[(size_t)b * A.K + j0], a, e);
-        Cx<double> mu[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const Cx<double> w = cmulc(nup[r], up(e[r]));
-            const Cx<double> ad = a[r];
-            const double f = 2.0 * A.tau * A.g * (w.re * ad.im - w.im * ad.re);
-            mu[r] = Cx<double>{w.re + f * ad.re, w.im + f * ad.im};
-            buf[t + r * q] = mu[r];
-        }
-        __syncthreads();
-        Cx<double>* nu = adj_half_kick<R>(A, buf, scr, false);         // nu_{j0}
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = t + r * q;
-            Lam_b[(size_t)nn * n + m] = dcx{(double)nu[m].re, (double)nu[m].im};
-        }
-        __syncthreads();
-        if (nn == 0) break;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) buf[t + r * q] = mu[r];
-        __syncthreads();
-        res = adj_half_kick<R>(A, buf, scr, true);               // nu'_{j0-1}
-        if (res != buf) {
-            Cx<double> v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = res[t + r * q];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < 4; ++r) buf[t + r * q] = v[r];
-        }
-        __syncthreads();
-    }
+    const Lds L = lds_carve<NN>(smem_raw);
+    const int b = blockIdx.x;
+    double v0[16], v1[16];
+    setup<NN>(A, L, v0, v1);
+    dcx* Lam_b = A.Lam + (size_t)b * (A.N + 1) * NN;
+    const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
+    Cd x[16];
+    load_state<NN>(x, A.target);
+    store_state<NN>(Lam_b + (size_t)A.N * NN, x);
+    kick<NN, true>(x, L, reinterpret_cast<const Cd*>(A.Kh));       // nu'_{K-1}
+    for (int nn = A.N - 1; nn >= 0; --nn)
+        adj_run<NN, R>(A, L, b, A.s[nn], A.s[nn + 1], x, v0, v1, traj_b,
+                       Lam_b + (size_t)nn * NN, nn > 0 ? 2 : 1, false, false);
 }
 
 // Slice n of instance b: forward from psi(t_n), adjoint from nu(t_{n+1}), gradient, update.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_gpe_slice(GpeArgs A) {
+template <int NN, typename R>
+__global__ __launch_bounds__(NN / 16) void k_gpe_slice(GpeArgs A) {
     extern __shared__ unsigned char smem_raw[];
-    Cx<double>* buf = reinterpret_cast<Cx<double>*>(smem_raw);
-    Cx<double>* scr = buf + A.n;
-    double* red = reinterpret_cast<double*>(scr + A.n);
-    const int nn = blockIdx.x, b = blockIdx.y, n = A.n, q = n >> 2, t = threadIdx.x;
-    double v0[4], v1[4];
-    load_pot<R>(A, v0, v1);
+    const Lds L = lds_carve<NN>(smem_raw);
+    const int nn = blockIdx.x, b = blockIdx.y;
+    double v0[16], v1[16];
+    setup<NN>(A, L, v0, v1);
     const int j0 = A.s[nn], j1 = A.s[nn + 1];
-    Cx<R>* traj_b = reinterpret_cast<Cx<R>*>(A.traj) + (size_t)b * A.K * n;
-    const dcx* Psi_b = A.Psi + (size_t)b * (A.N + 1) * n;
-    const dcx* Lam_b = A.Lam + (size_t)b * (A.N + 1) * n;
-    first_half_kick<R>(A, Psi_b + (size_t)nn * n, buf, scr);
-    forward_steps<R>(A, b, j0, j1, buf, scr, v0, v1, traj_b, nullptr, false);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const dcx v = Lam_b[(size_t)(nn + 1) * n + t + r * q];
-        buf[t + r * q] = Cx<double>{v.re, v.im};
-    }
-    __syncthreads();
-    Cx<double>* res = adj_half_kick<R>(A, buf, scr, false);            // nu'_{j1-1}
-    if (res != buf) {
-        Cx<double> v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = res[t + r * q];
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) buf[t + r * q] = v[r];
-        __syncthreads();
-    }
+    Cx<R>* traj_b = reinterpret_cast<Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
+    const dcx* Psi_b = A.Psi + (size_t)b * (A.N + 1) * NN;
+    const dcx* Lam_b = A.Lam + (size_t)b * (A.N + 1) * NN;
+    Cd x[16];
+    load_state<NN>(x, Psi_b + (size_t)nn * NN);
+    kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));      // a_{j0}
+    fwd_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b, nullptr, false);
+    load_state<NN>(x, Lam_b + (size_t)(nn + 1) * NN);
+    kick<NN, true>(x, L, reinterpret_cast<const Cd*>(A.Kh));       // nu'_{j1-1}
     const bool upd = A.update && (A.active == nullptr || A.active[b] != 0);
-    adjoint_steps<R>(A, b, j0, j1, buf, scr, v0, v1, traj_b, nullptr, 0, true, upd, red);
+    adj_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b, nullptr, 0, true, upd);
 }
 
 }  // namespace
@@ -527,9 +454,9 @@ struct GpeExt {
     double L = 0, g = 0, V2 = 0, dx = 0;
     double* V0 = nullptr;
     double* V1 = nullptr;
-    void* tw = nullptr;
-    void* Kh = nullptr;
-    void* Kf = nullptr;
+    dcx* tab = nullptr;
+    dcx* Kh = nullptr;
+    dcx* Kf = nullptr;
     dcx* Psi = nullptr;
     dcx* Lam = nullptr;
     dcx* psi0 = nullptr;
@@ -544,7 +471,7 @@ static void gpe_free(ism_problem* p) {
 
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision) {
     const size_t rs = precision == ISM_FP64 ? 16 : 8;
-    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + 3 * n * rs;
+    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 768) * 16;
 }
 
 static GpeArgs gpe_args(ism_problem* p) {
@@ -561,11 +488,10 @@ static GpeArgs gpe_args(ism_problem* p) {
     A.V0 = x->V0;
     A.V1 = x->V1;
     A.V2 = x->V2;
-    A.tw = x->tw;
+    A.tab = x->tab;
     A.Kh = x->Kh;
     A.Kf = x->Kf;
     A.u = p->u;
-    A.alpha = p->alpha;
     A.Psi = x->Psi;
     A.Lam = x->Lam;
     A.psi0 = x->psi0;
@@ -577,9 +503,42 @@ static GpeArgs gpe_args(ism_problem* p) {
     return A;
 }
 
-static size_t gpe_shmem(int n, int prec) {
-    (void)prec;   // the LDS-resident state is FP64 in both precisions
-    return 2 * (size_t)n * 16 + 16 * sizeof(double);
+// exchange buffer (padded), kinetic factors, twiddle tables, reduction slots; FP64 in both
+// precisions
+static size_t gpe_shmem(int n) {
+    return ((size_t)n + n / 16 + n + 768) * sizeof(dcx) + 16 * sizeof(double);
+}
+
+template <typename R>
+static void gpe_launch_sweeps(const GpeArgs& A, hipStream_t st, size_t shm) {
+    if (A.n == 4096) {
+        hipLaunchKernelGGL((k_gpe_fwd_sweep<4096, R>), dim3(A.B), dim3(256), shm, st, A);
+        hipLaunchKernelGGL((k_gpe_adj_sweep<4096, R>), dim3(A.B), dim3(256), shm, st, A);
+    } else {
+        hipLaunchKernelGGL((k_gpe_fwd_sweep<1024, R>), dim3(A.B), dim3(64), shm, st, A);
+        hipLaunchKernelGGL((k_gpe_adj_sweep<1024, R>), dim3(A.B), dim3(64), shm, st, A);
+    }
+}
+
+template <typename R>
+static void gpe_launch_slice(const GpeArgs& A, hipStream_t st, size_t shm) {
+    if (A.n == 4096)
+        hipLaunchKernelGGL((k_gpe_slice<4096, R>), dim3(A.N, A.B), dim3(256), shm, st, A);
+    else
+        hipLaunchKernelGGL((k_gpe_slice<1024, R>), dim3(A.N, A.B), dim3(64), shm, st, A);
+}
+
+template <int NN, typename R>
+static hipError_t gpe_set_shmem(int shm) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gpe_fwd_sweep<NN, R>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_gpe_adj_sweep<NN, R>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_gpe_slice<NN, R>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+    return e;
 }
 
 template <typename R>
@@ -588,11 +547,9 @@ static int gpe_boundary_t(ism_problem* p, double* Jhist_k, double fid_stop, bool
     A.Jhist = Jhist_k;
     A.active = use_active ? p->active : nullptr;
     A.fid_stop = fid_stop;
-    const size_t shm = gpe_shmem(A.n, p->precision);
     {
         TimeScope ts(p, KID_GPE_SWEEP);
-        hipLaunchKernelGGL(k_gpe_fwd_sweep<R>, dim3(p->B), dim3(A.n / 4), shm, p->stream, A);
-        hipLaunchKernelGGL(k_gpe_adj_sweep<R>, dim3(p->B), dim3(A.n / 4), shm, p->stream, A);
+        gpe_launch_sweeps<R>(A, p->stream, gpe_shmem(A.n));
     }
     if (hipGetLastError() != hipSuccess) return ISM_E_DEVICE;
     p->bvalid = true;
@@ -606,10 +563,9 @@ static int gpe_slice_t(ism_problem* p, int update, double rho, double* grad, boo
     A.rho = rho;
     A.update = update;
     A.active = use_active ? p->active : nullptr;
-    const size_t shm = gpe_shmem(A.n, p->precision);
     {
         TimeScope ts(p, KID_GPE_SLICE);
-        hipLaunchKernelGGL(k_gpe_slice<R>, dim3(p->N, p->B), dim3(A.n / 4), shm, p->stream, A);
+        gpe_launch_slice<R>(A, p->stream, gpe_shmem(A.n));
     }
     if (hipGetLastError() != hipSuccess) return ISM_E_DEVICE;
     if (update) p->bvalid = false;
@@ -633,16 +589,6 @@ int gpe_copy_state(ism_problem* p, double* out, int which_end) {
     return copy_rows_out(p, out, base, n * sizeof(dcx), (size_t)(p->N + 1) * n * sizeof(dcx), p->B);
 }
 
-template <typename R>
-static int upload_cx(ism_problem* p, void** dst, const std::vector<dcx>& v) {
-    std::vector<R> h(2 * v.size());
-    for (size_t i = 0; i < v.size(); ++i) {
-        h[2 * i] = (R)v[i].re;
-        h[2 * i + 1] = (R)v[i].im;
-    }
-    return dev_upload(p, dst, h.data(), h.size() * sizeof(R));
-}
-
 int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, const double* V1,
                double V2, const double* psi0, const double* target) {
     GpeExt* x = new (std::nothrow) GpeExt();
@@ -660,8 +606,18 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
     if ((st = dev_upload(p, (void**)&x->psi0, psi0, n * sizeof(dcx)))) return st;
     if ((st = dev_upload(p, (void**)&x->target, target, n * sizeof(dcx)))) return st;
     const double PI = 3.14159265358979323846;
-    std::vector<dcx> tw(n), kh(n), kf(n);
-    for (int t = 0; t < n; ++t) tw[t] = dcx{cos(2 * PI * t / n), -sin(2 * PI * t / n)};
+    // twiddles e^{-2 pi i e/m} with the exponent reduced exactly, in FP64
+    auto root = [&](long long e, long long m) {
+        e %= m;
+        return dcx{cos(2 * PI * (double)e / (double)m), -sin(2 * PI * (double)e / (double)m)};
+    };
+    std::vector<dcx> tab(768), kh(n), kf(n);
+    for (int r = 0; r < 16; ++r)
+        for (int k = 0; k < 16; ++k) {
+            tab[r * 16 + k] = root((long long)r * k, 256);              // pass 2
+            tab[256 + r * 16 + k] = root(16LL * r * k, n);              // pass 3, high part
+            tab[512 + r * 16 + k] = root((long long)r * k, n);          // pass 3, low part
+        }
     for (int m = 0; m < n; ++m) {
         const int f = m < n / 2 ? m : m - n;            // fftfreq ordering
         const double k = 2 * PI * f / L;
@@ -670,27 +626,20 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
         kf[m] = dcx{cos(2 * ph) / n, sin(2 * ph) / n};
     }
     const bool f64 = p->precision == ISM_FP64;
-    if ((st = upload_cx<double>(p, &x->tw, tw))) return st;       // tables stay FP64
-    if ((st = upload_cx<double>(p, &x->Kh, kh))) return st;
-    if ((st = upload_cx<double>(p, &x->Kf, kf))) return st;
+    if ((st = dev_upload(p, (void**)&x->tab, tab.data(), tab.size() * sizeof(dcx)))) return st;
+    if ((st = dev_upload(p, (void**)&x->Kh, kh.data(), kh.size() * sizeof(dcx)))) return st;
+    if ((st = dev_upload(p, (void**)&x->Kf, kf.data(), kf.size() * sizeof(dcx)))) return st;
     const size_t nb = (size_t)p->B * (p->N + 1) * n * sizeof(dcx);
     if ((st = dev_alloc(p, (void**)&x->Psi, nb))) return st;
     if ((st = dev_alloc(p, (void**)&x->Lam, nb))) return st;
     if ((st = dev_alloc(p, &x->traj, (size_t)p->B * p->K * n * (f64 ? 16 : 8)))) return st;
-    const size_t shm = gpe_shmem(n, p->precision);
-    const hipError_t e1 = f64 ? hipFuncSetAttribute((const void*)k_gpe_fwd_sweep<double>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)
-                              : hipFuncSetAttribute((const void*)k_gpe_fwd_sweep<float>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    const hipError_t e2 = f64 ? hipFuncSetAttribute((const void*)k_gpe_adj_sweep<double>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)
-                              : hipFuncSetAttribute((const void*)k_gpe_adj_sweep<float>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    const hipError_t e3 = f64 ? hipFuncSetAttribute((const void*)k_gpe_slice<double>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm)
-                              : hipFuncSetAttribute((const void*)k_gpe_slice<float>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return ISM_E_DEVICE;
+    const int shm = (int)gpe_shmem(n);
+    hipError_t e;
+    if (n == 4096)
+        e = f64 ? gpe_set_shmem<4096, double>(shm) : gpe_set_shmem<4096, float>(shm);
+    else
+        e = f64 ? gpe_set_shmem<1024, double>(shm) : gpe_set_shmem<1024, float>(shm);
+    if (e != hipSuccess) return ISM_E_DEVICE;
     return ISM_OK;
 }
 
