@@ -17,6 +17,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,74 @@ sys.path.insert(0, ROOT)
 
 METRIC = "propagation steps/s (fwd+adjoint) FP32 vs plain FP64 ISM; p50/p99 solve latency"
 PEAK_ALU = 78.6e12       # non-packed FP32 and FP64 vector FMA rate: 256 CU x 64 lanes x 2 x 2.4 GHz
+
+# HBM traffic of the dominant kernel, from two rocprofv3 counter runs of this script
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each divided by what the same counter
+# reads per KiB actually moved by a plain streaming kernel of known size (--copy-calibration).
+# It holds for the kernel sources it was taken on (sha256 over TRAFFIC_SOURCES); after any
+# change to them the field is reported as null until the counters are taken again.
+TRAFFIC_SOURCES = ["paper_1603_01237_amd/csrc/k_sparse.hip",
+                   "paper_1603_01237_amd/csrc/ism_internal.h"]
+TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 54511.9, "write_kib": 112896.0,
+           "copy_fetch_per_kib": 0.50001, "copy_write_per_kib": 1.0,
+           "sha256": "cbb4edfda02e145587a23cdd37c888e0d1df44f959572598e33455f3aadc4a5e"}
+COPY_BYTES = 1 << 30
+
+
+def _sources_sha():
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel):
+    t = TRAFFIC
+    if kernel != t["kernel"] or t["sha256"] is None or t["sha256"] != _sources_sha():
+        return None
+    return 1024.0 * (t["fetch_kib"] / t["copy_fetch_per_kib"]
+                     + t["write_kib"] / t["copy_write_per_kib"])
+
+
+def copy_calibration():
+    """A plain streaming kernel of known size (reads COPY_BYTES, writes COPY_BYTES), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = COPY_BYTES // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"kernel": "elementwise neg", "read_bytes": COPY_BYTES,
+                                           "write_bytes": COPY_BYTES, "launches": 3}}), flush=True)
+
+
+def serving_sample(n_req, iters_per_round=10, max_running=64):
+    """Replay of the first n_req requests of the seeded 200 req/s serving trace at their
+    arrival times (FP32 mixed; stop at F >= 0.99 or 200 iterations)."""
+    import problems
+    from paper_1603_01237_amd import Server
+    from paper_1603_01237_amd.serve import latency_summary, replay
+    trace = problems.serving_trace()[:n_req]
+    items = [(r["arrival"] - trace[0]["arrival"], problems.request_problem(r),
+              dict(max_iter=200, rho=problems.SERVE_RHO[r["type"]], fid_stop=0.99,
+                   precision="fp32")) for r in trace]
+    with Server(200 << 30, iters_per_round=iters_per_round, max_running=max_running) as s:
+        recs, wall = replay(s, items, timeout=600.0, report_every=10.0,
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+        st = s.stats()
+    out = latency_summary(recs, wall)
+    out.update({"busy_frac": st["busy_s"] / wall if wall > 0 else None,
+                "peak_device_GB": st["bytes_peak"] / 1e9,
+                "mean_iters": float(sum(r["iters"] for r in recs) / max(len(recs), 1)),
+                "reached_F099": int(sum(r["F"] >= 0.99 for r in recs)),
+                "sample": f"first {n_req} requests of the seeded 200 req/s trace (spin d in "
+                          "{4,16,64,256}, rotor j<=10/20/40, GPE n=1024/4096; K log-uniform "
+                          "1000..20000, N 16..128), arrival-time replay, FP32 mixed, stop at "
+                          "F>=0.99 or 200 iterations"})
+    return out
 
 
 def _sparse_row_costs(prob):
@@ -106,6 +175,10 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=3, help="oracle instances timed (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the streaming kernel that scales the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the multi-GPU sharding of ISM slices and "
@@ -115,6 +188,9 @@ def main():
     import torch
     import problems
     torch.cuda.init()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     stream = torch.cuda.current_stream().cuda_stream
     prob = problems.rotor(batch=args.batch)
     B = prob.batch
@@ -130,6 +206,9 @@ def main():
     launches, tot_ms = kt[dom]
     flops = algorithmic_flops(prob, r32["info"]["taylor_m"], r32["info"]["taylor_S"], B)
     achieved = flops.get(dom, 0.0) / (tot_ms / launches * 1e-3) if dom in flops else 0.0
+    per_launch = {k: {"launches": v[0], "avg_ms": v[1] / v[0],
+                      "algorithmic_TFLOP": flops[k] / 1e12 if k in flops else None}
+                  for k, v in kt.items()}
     out = {
         "metric": METRIC,
         "value": value,
@@ -148,7 +227,10 @@ def main():
                    "precision": "FP32 mixed (FP64 generator data, overlaps, boundaries)"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
                      "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU,
-                     "traffic": None},
+                     "traffic": traffic_bytes(dom),
+                     "avg_launch_ms": tot_ms / launches,
+                     "algorithmic_flop_per_launch": flops.get(dom)},
+        "kernels": per_launch,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
         "taylor": {"m": r32["info"]["taylor_m"], "S": r32["info"]["taylor_S"]},
         "final_F_mean": r32["F_mean"],
@@ -164,6 +246,8 @@ def main():
             "final_F_abs_diff_vs_fp32": abs(r64["F_mean"] - r32["F_mean"])}
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample)
+    if args.serve > 0:
+        out["serving"] = serving_sample(args.serve)
     print(json.dumps(out), flush=True)
 
 

@@ -10,11 +10,14 @@ import numpy as np
 from ._lib import REQ_DONE, REQ_FAILED, Server
 
 
-def replay(server: Server, items, idle_sleep: float = 2e-4, timeout: float = 600.0):
+def replay(server: Server, items, idle_sleep: float = 2e-4, timeout: float = 600.0,
+           report_every: float = 0.0, log=print):
     """items: list of (arrival_s, problem, submit-kwargs) sorted by arrival.  Returns
     (records, wall_s) with one record per item: ticket, state, status, iters, J, F,
-    latency_s, queue_s, u (final controls or None)."""
+    latency_s, queue_s, u (final controls or None).  With report_every > 0 a progress
+    line (submitted / finished / queued / running) is logged at that interval."""
     t0 = Server.clock()
+    t_rep = 0.0
     pending = {}
     records = [None] * len(items)
     i = 0
@@ -27,8 +30,12 @@ def replay(server: Server, items, idle_sleep: float = 2e-4, timeout: float = 600
             arr, prob, kw = items[i]
             pending[server.submit(prob, t_arrival=t0 + arr, **kw)] = i
             i += 1
-        server.progress()
+        nq, nr = server.progress()
         st = server.stats()
+        if report_every > 0 and now - t_rep >= report_every:
+            t_rep = now
+            log(f"replay t={now:.1f}s submitted={i} finished={st['completed'] + st['failed']} "
+                f"queued={nq} running={nr}")
         finished = st["completed"] + st["failed"]
         if finished != done_seen:
             done_seen = finished
