@@ -128,13 +128,83 @@ def algorithmic_flops(prob, m, S, B):
     return {"sp_assemble": assemble, "sp_slice": slice_}
 
 
-def run_gpu(prec, prob, steps, warmup, stream_ptr):
+PEAK_MFMA = {"fp32": 157.3e12, "fp64": 78.6e12}    # dense MFMA, v_mfma_*_16x16x4
+PEAK_CU_FP64 = 78.6e12 / 256                       # one CU (a sequential sweep is one workgroup)
+
+
+def gate_gemm_flops(prob, dp):
+    """MFMA work of one ISM iteration of the gate path (path precision), 8 d^3 flops per
+    complex d x d x d product: the assembly chain P_j = U_j P_{j-1} (K - N products), the
+    slice right-hand sides M_n^+ phi_{n+1} (N) and [X_j | Y_j] = P_{j-1} [phi_n | .]
+    (K - N products of twice the width)."""
+    K, N = prob.K, prob.N
+    return 8.0 * dp ** 3 * (3 * K - 2 * N)
+
+
+def gpe_sweep_flops(prob):
+    """FFT work of the two sequential sweeps of one iteration: 2K steps of two length-n
+    transforms at 5 n log2 n flops each (pointwise work not counted)."""
+    import math
+    return 2.0 * prob.K * 2 * 5 * prob.n * math.log2(prob.n) * prob.batch
+
+
+def other_workloads(stream, iters_gate=2, iters_gpe=2):
+    """The paper's other benchmark shapes: the two-spin solve (latency), gate synthesis
+    on MFMA and the condensate (sequential FFT sweeps)."""
+    import problems
+    out = {}
+    p0 = problems.spin2()
+    r = {prec: run_gpu(prec, p0, p0.iters, 1, stream, timing=False) for prec in ("fp64", "fp32")}
+    out["spins_d4"] = {
+        "workload": f"two coupled spins, d=4, K={p0.K}, N={p0.N}, {p0.iters} iterations (one solve)",
+        "solve_ms": {k: v["seconds"] * 1e3 for k, v in r.items()},
+        "useful_steps_per_s": {k: 2 * p0.K * p0.iters / v["seconds"] for k, v in r.items()},
+        "final_F": {k: v["F_mean"] for k, v in r.items()}}
+    pg = problems.spin_chain_gate()
+    r = {prec: run_gpu(prec, pg, iters_gate, 1, stream) for prec in ("fp32", "fp64")}
+    dp = pg.d
+    ent = {"workload": f"gate synthesis, 8-spin chain d={pg.d}, C={pg.C}, K={pg.K}, N={pg.N}",
+           "ms_per_iteration": {k: v["seconds"] / iters_gate * 1e3 for k, v in r.items()},
+           "useful_matrix_steps_per_s": {k: 2 * pg.K * iters_gate / v["seconds"]
+                                         for k, v in r.items()},
+           "kernels_ms_per_iteration": {k: {n: t[1] / iters_gate for n, t in v["kernels"].items()}
+                                        for k, v in r.items()}}
+    for prec, v in r.items():
+        launches, ms = v["kernels"]["gate_gemm"]
+        ach = gate_gemm_flops(pg, dp) * iters_gate / (ms * 1e-3)
+        ent[f"roofline_{prec}"] = {"bound": "mfma", "kernel": "gate_gemm (all batched GEMMs)",
+                                   "achieved": ach / 1e12, "peak": PEAK_MFMA[prec] / 1e12,
+                                   "unit": "TFLOP/s", "frac": ach / PEAK_MFMA[prec]}
+    out["gate_d256"] = ent
+    pe = problems.gpe()
+    r = {prec: run_gpu(prec, pe, iters_gpe, 1, stream) for prec in ("fp32", "fp64")}
+    ent = {"workload": f"condensate, n={pe.n}, K={pe.K}, N={pe.N}, g={pe.g}",
+           "ms_per_iteration": {k: v["seconds"] / iters_gpe * 1e3 for k, v in r.items()},
+           "useful_steps_per_s": {k: 2 * pe.K * iters_gpe / v["seconds"] for k, v in r.items()},
+           "kernels_ms_per_iteration": {k: {n: t[1] / iters_gpe for n, t in v["kernels"].items()}
+                                        for k, v in r.items()}}
+    for prec, v in r.items():
+        launches, ms = v["kernels"]["gpe_sweep"]
+        ach = gpe_sweep_flops(pe) * iters_gpe / (ms * 1e-3)
+        ent[f"roofline_{prec}"] = {"bound": "alu, one CU (sequential sweep)",
+                                   "kernel": "gpe fwd+adj sweeps", "achieved": ach / 1e9,
+                                   "peak": PEAK_CU_FP64 / 1e9, "unit": "GFLOP/s",
+                                   "frac": ach / PEAK_CU_FP64,
+                                   "us_per_step": ms * 1e3 / iters_gpe / (2 * pe.K)}
+    out["gpe_n4096"] = ent
+    return out
+
+
+def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True):
+    """Warm-up iterations, controls reset to u0, then `steps` timed iterations (per-kernel
+    HIP events on the handle's stream when `timing`)."""
     import torch
     from paper_1603_01237_amd import _lib
     h = _lib.from_problem(prob, precision=prec, stream=stream_ptr)
     h.iterate(warmup, prob.rho, record=False)
+    h.set_controls(prob.u0)
     torch.cuda.synchronize()
-    h.set_timing(True)
+    h.set_timing(timing)
     h.kernel_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -175,6 +245,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=3, help="oracle instances timed (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the two-spin, gate and condensate workloads")
     ap.add_argument("--serve", type=int, default=0,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -185,6 +257,9 @@ def main():
               "instances is a design (see the design notes), not part of this build",
               file=sys.stderr)
         sys.exit(2)
+    # more hardware queues than HIP's default 4, so that the streams of concurrently
+    # served requests run side by side (set before the HIP runtime initialises)
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     import torch
     import problems
     torch.cuda.init()
@@ -246,6 +321,8 @@ def main():
             "final_F_abs_diff_vs_fp32": abs(r64["F_mean"] - r32["F_mean"])}
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample)
+    if not args.no_workloads:
+        out["workloads"] = other_workloads(stream)
     if args.serve > 0:
         out["serving"] = serving_sample(args.serve)
     print(json.dumps(out), flush=True)

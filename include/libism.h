@@ -82,6 +82,10 @@ typedef struct ism_options {
     void* stream;           /* hipStream_t to issue work on; NULL => library-owned stream */
     int io_device;          /* 1: pointers of set/get_controls, forward, adjoint, gradient,
                                fidelity and the J history are device pointers (default 0) */
+    int alloc_async;        /* 1: the handle's device memory is allocated and freed
+                               stream-ordered on its stream (hipMallocAsync / hipFreeAsync), so
+                               creating and destroying the handle never synchronises the whole
+                               device (default 0: hipMalloc / hipFree) */
 } ism_options;
 
 /* Fill *opt with the defaults listed above.  opt must not be NULL. */

@@ -41,7 +41,7 @@ class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("kind", ct.c_int), ("batch", ct.c_int),
                 ("h0_batched", ct.c_int), ("alpha", ct.POINTER(ct.c_double)),
                 ("alpha_len", ct.c_int), ("device", ct.c_int), ("stream", ct.c_void_p),
-                ("io_device", ct.c_int)]
+                ("io_device", ct.c_int), ("alloc_async", ct.c_int)]
 
 
 class Info(ct.Structure):

@@ -85,7 +85,7 @@ TimeScope::~TimeScope() {
 int dev_alloc(ism_problem* p, void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) bytes = 16;
-    const hipError_t e = hipMalloc(ptr, bytes);
+    const hipError_t e = p->async_alloc ? hipMallocAsync(ptr, bytes, p->stream) : hipMalloc(ptr, bytes);
     if (e != hipSuccess) {
         *ptr = nullptr;
         return hip_status(e);
@@ -138,6 +138,7 @@ int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism
     p->tau = T / K;
     p->device = o->device;
     p->io_device = o->io_device;
+    p->async_alloc = o->alloc_async != 0;
     ISM_TRY_HIP(hipSetDevice(o->device));
     if (o->stream) {
         p->stream = (hipStream_t)o->stream;
@@ -443,6 +444,7 @@ void ism_default_options(ism_options* o) {
     o->device = 0;
     o->stream = nullptr;
     o->io_device = 0;
+    o->alloc_async = 0;
 }
 
 const char* ism_status_string(int s) {
@@ -469,8 +471,14 @@ void ism_problem_destroy(ism_problem* p) {
         hipEventDestroy(t.second.second);
     }
     for (hipEvent_t e : p->event_pool) hipEventDestroy(e);
-    for (void* a : p->allocs) hipFree(a);
-    if (p->own_stream && p->stream) hipStreamDestroy(p->stream);
+    for (void* a : p->allocs) {
+        if (p->async_alloc)
+            (void)hipFreeAsync(a, p->stream);
+        else
+            (void)hipFree(a);
+    }
+    if (p->async_alloc && p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
 }
 

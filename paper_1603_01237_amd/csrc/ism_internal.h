@@ -109,6 +109,7 @@ struct ism_problem {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool async_alloc = false;   // stream-ordered allocation on `stream`
     int io_device = 0;
     size_t bytes = 0;
     std::vector<void*> allocs;

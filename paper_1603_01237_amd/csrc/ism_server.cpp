@@ -149,6 +149,7 @@ int create_handle(ism_server* s, Req* r) {
     o.precision = r->r.precision;
     o.kind = r->r.kind;
     o.device = s->device;
+    o.alloc_async = 1;      // retiring a request must not wait for the other requests' work
     const ism_request& q = r->r;
     if (q.model == ISM_REQ_GPE)
         return ism_problem_create_gpe(&r->h, q.n_grid, q.L, q.g, q.V0, q.V1, q.V2, q.psi0,
