@@ -226,7 +226,10 @@ static int sp_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bo
     }
     {
         TimeScope ts(p, KID_SP_ASSEMBLE);
-        ISM_TRY_HIP(sp_launch_assemble(a, p->variant, p->precision, p->stream));
+        if (p->tri)
+            ISM_TRY_HIP(sp_launch_assemble_tri(a, p->precision, p->stream));
+        else
+            ISM_TRY_HIP(sp_launch_assemble(a, p->variant, p->precision, p->stream));
     }
     BndArgs bnd{};
     bnd.B = p->B;
@@ -318,6 +321,12 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
     }
     const int vi = sp_variant_index(CG, WC, realh ? 1 : 0, d);
     if (vi < 0) return ISM_E_UNSUPPORTED;
+    // one real control operator with entries only at (r, r +- 1) and a diagonal H0
+    bool tri = CG == 1 && realh && !offdiag && WC <= 2 && sp_tri_supported(d);
+    for (int r = 0; tri && r < d; ++r)
+        for (const auto& e : rows[0][r])
+            if (e.first != r - 1 && e.first != r + 1) tri = false;
+    p->tri = tri ? 1 : 0;
     p->CG = CG;
     p->WC = WC;
     p->has_offdiag = offdiag ? 1 : 0;

@@ -95,6 +95,9 @@ int sp_variant_index(int CG, int WC, int realh, int d);
 hipError_t sp_launch_params(const SpArgs& a, const double* h0norm, const double* gnorm,
                             int precision, hipStream_t st, int* flags);
 hipError_t sp_launch_assemble(const SpArgs& a, int variant, int precision, hipStream_t st);
+// assembly for one real tridiagonal control operator and a diagonal H0 (several rows per lane)
+hipError_t sp_launch_assemble_tri(const SpArgs& a, int precision, hipStream_t st);
+bool sp_tri_supported(int d);
 hipError_t sp_launch_slice(const SpArgs& a, int variant, int precision, hipStream_t st);
 hipError_t sp_launch_boundary(const BndArgs& a, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* flag, hipStream_t st);
@@ -130,6 +133,7 @@ struct ism_problem {
 
     // sparse path
     int CG = 0, WC = 0, has_offdiag = 0, realh = 0, variant = -1;
+    int tri = 0;               // generator is one real operator coupling rows r, r +- 1 only
     double* h0diag = nullptr;
     int h0diag_stride = 0;
     int* gcol = nullptr;

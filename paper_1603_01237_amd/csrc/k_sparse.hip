@@ -143,13 +143,31 @@ __device__ __forceinline__ void gen_apply(const Gen<R, CGM, WCM, RH>& G, const X
     }
 }
 
+// Generator terms with the step's control values folded in (v_g G_g), formed once per step
+// so that a Taylor term costs no separate control multiplication.
+template <typename R, int CGM, int WCM, bool RH>
+__device__ __forceinline__ Gen<R, CGM, WCM, RH> scaled(const Gen<R, CGM, WCM, RH>& G,
+                                                       const R (&v)[CGM]) {
+    Gen<R, CGM, WCM, RH> S;
+#pragma unroll
+    for (int g = 0; g < CGM; ++g)
+#pragma unroll
+        for (int w = 0; w < WCM; ++w) {
+            S.addr[g][w] = G.addr[g][w];
+            S.vre[g][w] = v[g] * G.vre[g][w];
+            S.vim[g][w] = RH ? R(0) : v[g] * G.vim[g][w];
+        }
+    return S;
+}
+
 // x <- exp(-i (H - s) tau_sub) x, degree-m Taylor polynomial evaluated by Horner's rule
 // p <- x + A p / k (k = m..1): the small high-order terms are combined before they meet x,
 // so they are not lost to the rounding of x (which in FP32 would shorten the series the same
-// way at every step).  The generator is pre-scaled by tau_sub.
+// way at every step).  Gs holds the generator of the step, pre-scaled by tau_sub and by the
+// controls (see scaled()).
 template <typename R, int CGM, int WCM, bool RH, class X>
-__device__ __forceinline__ void fwd_substep(R& xr, R& xi, Diag<R> d0, const R (&v)[CGM],
-                                            const Gen<R, CGM, WCM, RH>& G, const X& ex, int r,
+__device__ __forceinline__ void fwd_substep(R& xr, R& xi, Diag<R> d0,
+                                            const Gen<R, CGM, WCM, RH>& Gs, const X& ex, int r,
                                             int m) {
     R pr = xr, pi = xi;
 #pragma unroll 1
@@ -157,15 +175,22 @@ __device__ __forceinline__ void fwd_substep(R& xr, R& xi, Diag<R> d0, const R (&
         ex.publish(0, r, pr);
         ex.publish(1, r, pi);
         ex.sync();
-        R gr[CGM], gi[CGM];
-        gen_apply(G, ex, 0, pr, pi, gr, gi);
-        ex.sync();
         R hr = d0.mul(pr), hi = d0.mul(pi);
 #pragma unroll
-        for (int g = 0; g < CGM; ++g) {
-            hr = fma(v[g], gr[g], hr);
-            hi = fma(v[g], gi[g], hi);
-        }
+        for (int g = 0; g < CGM; ++g)
+#pragma unroll
+            for (int w = 0; w < WCM; ++w) {
+                const R nr = ex.fetch(0, Gs.addr[g][w], pr);
+                const R ni = ex.fetch(1, Gs.addr[g][w], pi);
+                if (RH) {
+                    hr = fma(Gs.vre[g][w], nr, hr);
+                    hi = fma(Gs.vre[g][w], ni, hi);
+                } else {
+                    hr = fma(Gs.vre[g][w], nr, fma(-Gs.vim[g][w], ni, hr));
+                    hi = fma(Gs.vre[g][w], ni, fma(Gs.vim[g][w], nr, hi));
+                }
+            }
+        ex.sync();
         const R rk = rk_of(R(0), k - 1);     // 1/k
         pr = fma(hi, rk, xr);                // p <- x - i h / k
         pi = fma(-hr, rk, xi);
@@ -325,9 +350,8 @@ __device__ __forceinline__ void load_gen(const SpArgs& a, const ItemMap& im, dou
 }
 
 // control values of step j: v_g = u_{j,g} (g < C), 1 for the off-diagonal part of H0
-template <typename R, int CGM>
-__device__ __forceinline__ void load_controls(const SpArgs& a, int b, int j, R (&v)[CGM],
-                                              double (&ud)[CGM]) {
+template <int CGM>
+__device__ __forceinline__ void fetch_controls(const SpArgs& a, int b, int j, double (&ud)[CGM]) {
     const double* uj = a.u + ((size_t)b * a.K + j) * a.C;
 #pragma unroll
     for (int g = 0; g < CGM; ++g) {
@@ -335,7 +359,6 @@ __device__ __forceinline__ void load_controls(const SpArgs& a, int b, int j, R (
         if (g < a.C) x = uj[g];
         else if (g < a.CG && a.has_offdiag) x = 1.0;
         ud[g] = x;
-        v[g] = (R)x;
     }
 }
 
@@ -377,14 +400,19 @@ __global__ __launch_bounds__(256) void k_sp_assemble(SpArgs a) {
     const int col = item_ok ? im.item - n * a.d : 0;
     const int sn = a.s[n], L = a.s[n + 1] - sn;
     R xr = (im.valid && im.r == col) ? R(1) : R(0), xi = 0;
+    double unext[CGM];
+    fetch_controls<CGM>(a, im.b, sn, unext);
     for (int jl = 0; jl < a.LMAX; ++jl) {
         const bool act = im.valid && jl < L;
-        const int j = sn + (jl < L ? jl : L - 1);
         R v[CGM];
-        double ud[CGM];
-        load_controls(a, im.b, j, v, ud);
+#pragma unroll
+        for (int g = 0; g < CGM; ++g) v[g] = (R)unext[g];
+        // the next step's controls are requested before this step's series
+        const int jn = sn + (jl + 1 < L ? jl + 1 : L - 1);
+        fetch_controls<CGM>(a, im.b, jn, unext);
+        const Gen<R, CGM, WCM, RH> Gs = scaled(G, v);
         R nr = xr, ni = xi;
-        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, v, G, ex, im.r, m);
+        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, Gs, ex, im.r, m);
         if (act) {
             xr = nr;
             xi = ni;
@@ -423,14 +451,18 @@ __global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
         xi = (R)ph.im;
     }
     // forward sweep from phi_n (phase-less factor of the step map)
+    double unext[CGM];
+    fetch_controls<CGM>(a, im.b, sn, unext);
     for (int jl = 0; jl < a.LMAX; ++jl) {
         const bool act = im.valid && jl < L;
-        const int j = sn + (jl < L ? jl : L - 1);
         R v[CGM];
-        double ud[CGM];
-        load_controls(a, im.b, j, v, ud);
+#pragma unroll
+        for (int g = 0; g < CGM; ++g) v[g] = (R)unext[g];
+        const int jn = sn + (jl + 1 < L ? jl + 1 : L - 1);
+        fetch_controls<CGM>(a, im.b, jn, unext);
+        const Gen<R, CGM, WCM, RH> Gs = scaled(G, v);
         R nr = xr, ni = xi;
-        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, v, G, ex, im.r, m);
+        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, Gs, ex, im.r, m);
         if (act) {
             xr = nr;
             xi = ni;
@@ -448,12 +480,20 @@ __global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
     const double cph = cos(theta), sph = sin(theta);   // e^{-i theta} = cph - i sph
     const double beta_over_tau = ((double)a.K / (double)L) / a.tau;
     const bool upd = a.update && (a.active == nullptr || a.active[im.b] != 0);
+    fetch_controls<CGM>(a, im.b, sn + (a.LMAX - 1 < L ? a.LMAX - 1 : L - 1), unext);
     for (int jl = a.LMAX - 1; jl >= 0; --jl) {
         const bool act = im.valid && jl < L;
         const int j = sn + (jl < L ? jl : L - 1);
         R v[CGM];
         double ud[CGM];
-        load_controls(a, im.b, j, v, ud);
+#pragma unroll
+        for (int g = 0; g < CGM; ++g) {
+            ud[g] = unext[g];
+            v[g] = (R)ud[g];
+        }
+        // the previous step's controls (not yet updated: step j-1 is updated in the next
+        // pass of this loop) are requested before this step's series
+        if (jl > 0) fetch_controls<CGM>(a, im.b, sn + (jl - 1 < L ? jl - 1 : L - 1), unext);
         R yr[CGM], yi[CGM];
 #pragma unroll
         for (int c = 0; c < CGM; ++c) yr[c] = yi[c] = 0;
@@ -685,6 +725,133 @@ constexpr Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// Tridiagonal generators: one real symmetric control operator that couples row r only to
+// rows r-1 and r+1, and a diagonal H0 (the rotor's cos(theta) in the m = 0 basis).  Each
+// lane holds RPL consecutive rows, so only the two band edges of a lane cross lanes: a third
+// of the lane exchanges of the one-row-per-lane layout, whose assembly is bound by the LDS
+// crossbar that carries them.  In FP32 the diagonal tau_sub (H0_rr - s) is a single rounded
+// coefficient and its rounding residual delta_r is put back once per sub-step as the phase
+// e^{-i delta_r} (delta_r ~ 1e-9, so the commutator it leaves out is ~1e-10 per step).
+constexpr int RPL = 3;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    int gw = blockIdx.x * WPB + (threadIdx.x >> 6);
+    gw = __builtin_amdgcn_readfirstlane(gw);
+    const int b = gw / a.waves_per_inst;
+    if (b >= a.B) return;
+    const int wi = gw - b * a.waves_per_inst;
+    const int d = a.d, LPI = (d + RPL - 1) / RPL;
+    const int p = lane / LPI, li = lane - p * LPI;
+    const int item = wi * a.P + p;
+    const bool valid = p < a.P && item < a.items_per_inst;
+    const int n = valid ? item / d : 0;
+    const int col = valid ? item - n * d : 0;
+    const int r0 = li * RPL;
+    const TaylorP tp = a.tp[b];
+    const int m = __builtin_amdgcn_readfirstlane(tp.m);
+    const int S = __builtin_amdgcn_readfirstlane(tp.S);
+    const double ts = tp.tau_sub, sh = a.shift[b];
+    R dg[RPL], dl[RPL], Lc[RPL], Rc[RPL], xr[RPL], xi[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = r0 + q;
+        const bool ok = valid && r < d;
+        const double dd = ok ? (a.h0diag[(size_t)b * a.h0diag_stride + r] - sh) * ts : 0.0;
+        dg[q] = (R)dd;
+        dl[q] = (R)(dd - (double)dg[q]);
+        double lv = 0.0, rv = 0.0;
+        if (ok) {
+            for (int w = 0; w < a.WC; ++w) {
+                const int idx = r * a.WC + w;
+                const int c = a.gcol[idx];
+                const double v = a.gval[idx].re * ts;
+                if (c == r - 1) lv = v;
+                else if (c == r + 1) rv = v;
+            }
+        }
+        Lc[q] = (R)lv;
+        Rc[q] = (R)rv;
+        xr[q] = (ok && r == col) ? R(1) : R(0);
+        xi[q] = 0;
+    }
+    const int sn = a.s[n], L = a.s[n + 1] - sn;
+    const int left = (lane > 0 ? lane - 1 : 0) * 4, right = (lane < WAVE - 1 ? lane + 1 : lane) * 4;
+    const double* ub = a.u + (size_t)b * a.K;       // one control
+    double unext = ub[sn];
+    for (int jl = 0; jl < a.LMAX; ++jl) {
+        const bool act = valid && jl < L;
+        const R v = (R)unext;
+        unext = ub[sn + (jl + 1 < L ? jl + 1 : L - 1)];
+        R Ls[RPL], Rs[RPL], nr[RPL], ni[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            Ls[q] = v * Lc[q];
+            Rs[q] = v * Rc[q];
+            nr[q] = xr[q];
+            ni[q] = xi[q];
+        }
+        for (int sub = 0; sub < S; ++sub) {
+            R pr[RPL], pi[RPL];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                pr[q] = nr[q];
+                pi[q] = ni[q];
+            }
+#pragma unroll 1
+            for (int k = m; k >= 1; --k) {
+                const R lr = lane_fetch(left, pr[RPL - 1]), lim = lane_fetch(left, pi[RPL - 1]);
+                const R rr = lane_fetch(right, pr[0]), rim = lane_fetch(right, pi[0]);
+                R hr[RPL], hi[RPL];
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    const R pvr = q > 0 ? pr[q - 1] : lr, pvi = q > 0 ? pi[q - 1] : lim;
+                    const R nxr = q < RPL - 1 ? pr[q + 1] : rr, nxi = q < RPL - 1 ? pi[q + 1] : rim;
+                    hr[q] = fma(Rs[q], nxr, fma(Ls[q], pvr, dg[q] * pr[q]));
+                    hi[q] = fma(Rs[q], nxi, fma(Ls[q], pvi, dg[q] * pi[q]));
+                }
+                const R rk = rk_of(R(0), k - 1);
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    pr[q] = fma(hi[q], rk, nr[q]);        // p <- x - i h / k
+                    pi[q] = fma(-hr[q], rk, ni[q]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                nr[q] = pr[q];
+                ni[q] = pi[q];
+                if (sizeof(R) == 4) {                     // e^{-i delta} on the sub-step
+                    const R t = nr[q];
+                    nr[q] = fma(dl[q], ni[q], nr[q]);
+                    ni[q] = fma(-dl[q], t, ni[q]);
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                xr[q] = nr[q];
+                xi[q] = ni[q];
+            }
+        }
+    }
+    if (valid) {
+        R* M = reinterpret_cast<R*>(a.M);
+        const size_t o = (((size_t)b * a.N + n) * d + col) * d;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int r = r0 + q;
+            if (r < d) {
+                M[(o + r) * 2] = xr[q];
+                M[(o + r) * 2 + 1] = xi[q];
+            }
+        }
+    }
+}
+
+
 #define ISM_SP_DISPATCH(KERNEL, R, X, VI, GRID, BLOCK, SHMEM, ST, ARGS)                            \
     switch (VI) {                                                                                \
         case 0: launch_with_shm(KERNEL<R, 1, 2, true, X<R>>, GRID, BLOCK, SHMEM, ST, ARGS); break;  \
@@ -765,6 +932,23 @@ static hipError_t sp_launch_kernel(const SpArgs& a, int vi, int precision, hipSt
     }
     return hipGetLastError();
 }
+
+hipError_t sp_launch_assemble_tri(const SpArgs& a0, int precision, hipStream_t st) {
+    SpArgs a = a0;
+    const int LPI = (a.d + RPL - 1) / RPL;
+    a.P = WAVE / LPI;
+    a.items_per_inst = a.N * a.d;
+    a.waves_per_inst = (a.items_per_inst + a.P - 1) / a.P;
+    const long waves = (long)a.B * a.waves_per_inst;
+    const dim3 grid((unsigned)((waves + WPB - 1) / WPB)), block(WAVE * WPB);
+    if (precision == ISM_FP64)
+        hipLaunchKernelGGL(k_sp_assemble_tri<double>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_sp_assemble_tri<float>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+bool sp_tri_supported(int d) { return d >= 1 && d <= RPL * WAVE; }
 
 hipError_t sp_launch_assemble(const SpArgs& a, int vi, int precision, hipStream_t st) {
     return a.d <= WAVE ? sp_launch_kernel<XWave>(a, vi, precision, st, true)
