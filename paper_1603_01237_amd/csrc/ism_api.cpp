@@ -273,7 +273,10 @@ static int sp_slice_pass(ism_problem* p, int update, double rho, double* grad, b
     a.active = use_active ? p->active : nullptr;
     {
         TimeScope ts(p, KID_SP_SLICE);
-        ISM_TRY_HIP(sp_launch_slice(a, p->variant, p->precision, p->stream));
+        if (p->tri)
+            ISM_TRY_HIP(sp_launch_slice_tri(a, p->precision, p->stream));
+        else
+            ISM_TRY_HIP(sp_launch_slice(a, p->variant, p->precision, p->stream));
     }
     if (update) p->bvalid = false;
     return ISM_OK;

@@ -97,6 +97,7 @@ hipError_t sp_launch_params(const SpArgs& a, const double* h0norm, const double*
 hipError_t sp_launch_assemble(const SpArgs& a, int variant, int precision, hipStream_t st);
 // assembly for one real tridiagonal control operator and a diagonal H0 (several rows per lane)
 hipError_t sp_launch_assemble_tri(const SpArgs& a, int precision, hipStream_t st);
+hipError_t sp_launch_slice_tri(const SpArgs& a, int precision, hipStream_t st);
 bool sp_tri_supported(int d);
 hipError_t sp_launch_slice(const SpArgs& a, int variant, int precision, hipStream_t st);
 hipError_t sp_launch_boundary(const BndArgs& a, hipStream_t st);

@@ -734,6 +734,174 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 // e^{-i delta_r} (delta_r ~ 1e-9, so the commutator it leaves out is ~1e-10 per step).
 constexpr int RPL = 3;
 
+// Per-lane coefficients of the tridiagonal layout: rows r0 .. r0+RPL-1 of instance b,
+// scaled by tau_sub; dg the (rounded) diagonal, dl its FP32 rounding residual, Lc / Rc the
+// couplings to rows r-1 / r+1 (zero where absent or beyond d).
+template <typename R>
+__device__ __forceinline__ void tri_coeffs(const SpArgs& a, int b, int r0, bool valid, double ts,
+                                           R (&dg)[RPL], R (&dl)[RPL], R (&Lc)[RPL],
+                                           R (&Rc)[RPL]) {
+    const double sh = a.shift[b];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = r0 + q;
+        const bool ok = valid && r < a.d;
+        const double dd = ok ? (a.h0diag[(size_t)b * a.h0diag_stride + r] - sh) * ts : 0.0;
+        dg[q] = (R)dd;
+        dl[q] = (R)(dd - (double)dg[q]);
+        double lv = 0.0, rv = 0.0;
+        if (ok) {
+            for (int w = 0; w < a.WC; ++w) {
+                const int idx = r * a.WC + w;
+                const int c = a.gcol[idx];
+                const double v = a.gval[idx].re * ts;
+                if (c == r - 1) lv = v;
+                else if (c == r + 1) rv = v;
+            }
+        }
+        Lc[q] = (R)lv;
+        Rc[q] = (R)rv;
+    }
+}
+
+// Neighbour rows across the lane edges: the row below this lane's first row and the row
+// above its last row.
+template <typename R>
+__device__ __forceinline__ void tri_edges(const R (&xr)[RPL], const R (&xi)[RPL], int left,
+                                          int right, R& lr, R& li, R& rr, R& ri) {
+    lr = lane_fetch(left, xr[RPL - 1]);
+    li = lane_fetch(left, xi[RPL - 1]);
+    rr = lane_fetch(right, xr[0]);
+    ri = lane_fetch(right, xi[0]);
+}
+
+// h = (D + L shift_down + R shift_up) x on this lane's rows
+template <typename R>
+__device__ __forceinline__ void tri_apply(const R (&xr)[RPL], const R (&xi)[RPL], R lr, R li, R rr,
+                                          R ri, const R (&dg)[RPL], const R (&Ls)[RPL],
+                                          const R (&Rs)[RPL], R (&hr)[RPL], R (&hi)[RPL]) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const R pvr = q > 0 ? xr[q - 1] : lr, pvi = q > 0 ? xi[q - 1] : li;
+        const R nxr = q < RPL - 1 ? xr[q + 1] : rr, nxi = q < RPL - 1 ? xi[q + 1] : ri;
+        hr[q] = fma(Rs[q], nxr, fma(Ls[q], pvr, dg[q] * xr[q]));
+        hi[q] = fma(Rs[q], nxi, fma(Ls[q], pvi, dg[q] * xi[q]));
+    }
+}
+
+// x <- e^{-i delta} T_m(-i (D + V)) x for one sub-step (Horner, as fwd_substep)
+template <typename R>
+__device__ __forceinline__ void tri_fwd_substep(R (&nr)[RPL], R (&ni)[RPL], const R (&dg)[RPL],
+                                                const R (&dl)[RPL], const R (&Ls)[RPL],
+                                                const R (&Rs)[RPL], int left, int right, int m) {
+    R pr[RPL], pi[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        pr[q] = nr[q];
+        pi[q] = ni[q];
+    }
+#pragma unroll 1
+    for (int k = m; k >= 1; --k) {
+        R lr, li, rr, ri, hr[RPL], hi[RPL];
+        tri_edges(pr, pi, left, right, lr, li, rr, ri);
+        tri_apply(pr, pi, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+        const R rk = rk_of(R(0), k - 1);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            pr[q] = fma(hi[q], rk, nr[q]);                // p <- x - i h / k
+            pi[q] = fma(-hr[q], rk, ni[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        nr[q] = pr[q];
+        ni[q] = pi[q];
+        if (sizeof(R) == 4) {                             // e^{-i delta}
+            const R t = nr[q];
+            nr[q] = fma(dl[q], ni[q], nr[q]);
+            ni[q] = fma(-dl[q], t, ni[q]);
+        }
+    }
+}
+
+// One sub-step of the block exponential of adj_substep in the tridiagonal layout:
+// (y, chi) <- exp([[A^+, E^+], [0, A^+]]) (y, chi) and psi <- exp(A^+) psi, with
+// A^+ = +i (D + v G), E^+ = +i G (G the unscaled control operator), then e^{+i delta} on
+// all three (FP32).
+template <typename R>
+__device__ __forceinline__ void tri_adj_substep(R (&cr)[RPL], R (&ci)[RPL], R (&pr)[RPL],
+                                                R (&pi)[RPL], R (&yr)[RPL], R (&yi)[RPL],
+                                                const R (&dg)[RPL], const R (&dl)[RPL],
+                                                const R (&Lc)[RPL], const R (&Rc)[RPL],
+                                                const R (&Ls)[RPL], const R (&Rs)[RPL], R v,
+                                                int left, int right, int m) {
+    R qcr[RPL], qci[RPL], qpr[RPL], qpi[RPL], qyr[RPL], qyi[RPL];
+    const R zero[RPL] = {};
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        qcr[q] = cr[q];
+        qci[q] = ci[q];
+        qpr[q] = pr[q];
+        qpi[q] = pi[q];
+        qyr[q] = yr[q];
+        qyi[q] = yi[q];
+    }
+#pragma unroll 1
+    for (int k = m; k >= 1; --k) {
+        R clr, cli, crr, cri, plr, pli, prr, pri, ylr, yli, yrr, yri;
+        tri_edges(qcr, qci, left, right, clr, cli, crr, cri);
+        tri_edges(qpr, qpi, left, right, plr, pli, prr, pri);
+        tri_edges(qyr, qyi, left, right, ylr, yli, yrr, yri);
+        R gcr[RPL], gci[RPL], hpr[RPL], hpi[RPL], hyr[RPL], hyi[RPL];
+        tri_apply(qcr, qci, clr, cli, crr, cri, zero, Lc, Rc, gcr, gci);   // G chi
+        tri_apply(qpr, qpi, plr, pli, prr, pri, dg, Ls, Rs, hpr, hpi);
+        tri_apply(qyr, qyi, ylr, yli, yrr, yri, dg, Ls, Rs, hyr, hyi);
+        const R rk = rk_of(R(0), k - 1);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const R hcr = fma(v, gcr[q], dg[q] * qcr[q]), hci = fma(v, gci[q], dg[q] * qci[q]);
+            hyr[q] += gcr[q];                             // E^+ chi enters the y block
+            hyi[q] += gci[q];
+            qcr[q] = fma(-hci, rk, cr[q]);                // q <- x + i h / k
+            qci[q] = fma(hcr, rk, ci[q]);
+            qpr[q] = fma(-hpi[q], rk, pr[q]);
+            qpi[q] = fma(hpr[q], rk, pi[q]);
+            qyr[q] = fma(-hyi[q], rk, yr[q]);
+            qyi[q] = fma(hyr[q], rk, yi[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        cr[q] = qcr[q];
+        ci[q] = qci[q];
+        pr[q] = qpr[q];
+        pi[q] = qpi[q];
+        yr[q] = qyr[q];
+        yi[q] = qyi[q];
+        if (sizeof(R) == 4) {                             // e^{+i delta} on all three
+            R t = cr[q];
+            cr[q] = fma(-dl[q], ci[q], cr[q]);
+            ci[q] = fma(dl[q], t, ci[q]);
+            t = pr[q];
+            pr[q] = fma(-dl[q], pi[q], pr[q]);
+            pi[q] = fma(dl[q], t, pi[q]);
+            t = yr[q];
+            yr[q] = fma(-dl[q], yi[q], yr[q]);
+            yi[q] = fma(dl[q], t, yi[q]);
+        }
+    }
+}
+
+// Sum over the LPI lanes of one item; valid on the item's first lane.
+__device__ __forceinline__ double lanes_sum(double v, int lane, int li, int LPI) {
+    for (int off = 1; off < LPI; off <<= 1) {
+        const int src = lane + off < WAVE ? lane + off : WAVE - 1;
+        const double o = lane_fetch(src * 4, v);
+        if (li + off < LPI) v += o;
+    }
+    return v;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -752,28 +920,11 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
     const TaylorP tp = a.tp[b];
     const int m = __builtin_amdgcn_readfirstlane(tp.m);
     const int S = __builtin_amdgcn_readfirstlane(tp.S);
-    const double ts = tp.tau_sub, sh = a.shift[b];
     R dg[RPL], dl[RPL], Lc[RPL], Rc[RPL], xr[RPL], xi[RPL];
+    tri_coeffs(a, b, r0, valid, tp.tau_sub, dg, dl, Lc, Rc);
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-        const int r = r0 + q;
-        const bool ok = valid && r < d;
-        const double dd = ok ? (a.h0diag[(size_t)b * a.h0diag_stride + r] - sh) * ts : 0.0;
-        dg[q] = (R)dd;
-        dl[q] = (R)(dd - (double)dg[q]);
-        double lv = 0.0, rv = 0.0;
-        if (ok) {
-            for (int w = 0; w < a.WC; ++w) {
-                const int idx = r * a.WC + w;
-                const int c = a.gcol[idx];
-                const double v = a.gval[idx].re * ts;
-                if (c == r - 1) lv = v;
-                else if (c == r + 1) rv = v;
-            }
-        }
-        Lc[q] = (R)lv;
-        Rc[q] = (R)rv;
-        xr[q] = (ok && r == col) ? R(1) : R(0);
+        xr[q] = (valid && r0 + q < d && r0 + q == col) ? R(1) : R(0);
         xi[q] = 0;
     }
     const int sn = a.s[n], L = a.s[n + 1] - sn;
@@ -792,43 +943,7 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
             nr[q] = xr[q];
             ni[q] = xi[q];
         }
-        for (int sub = 0; sub < S; ++sub) {
-            R pr[RPL], pi[RPL];
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                pr[q] = nr[q];
-                pi[q] = ni[q];
-            }
-#pragma unroll 1
-            for (int k = m; k >= 1; --k) {
-                const R lr = lane_fetch(left, pr[RPL - 1]), lim = lane_fetch(left, pi[RPL - 1]);
-                const R rr = lane_fetch(right, pr[0]), rim = lane_fetch(right, pi[0]);
-                R hr[RPL], hi[RPL];
-#pragma unroll
-                for (int q = 0; q < RPL; ++q) {
-                    const R pvr = q > 0 ? pr[q - 1] : lr, pvi = q > 0 ? pi[q - 1] : lim;
-                    const R nxr = q < RPL - 1 ? pr[q + 1] : rr, nxi = q < RPL - 1 ? pi[q + 1] : rim;
-                    hr[q] = fma(Rs[q], nxr, fma(Ls[q], pvr, dg[q] * pr[q]));
-                    hi[q] = fma(Rs[q], nxi, fma(Ls[q], pvi, dg[q] * pi[q]));
-                }
-                const R rk = rk_of(R(0), k - 1);
-#pragma unroll
-                for (int q = 0; q < RPL; ++q) {
-                    pr[q] = fma(hi[q], rk, nr[q]);        // p <- x - i h / k
-                    pi[q] = fma(-hr[q], rk, ni[q]);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                nr[q] = pr[q];
-                ni[q] = pi[q];
-                if (sizeof(R) == 4) {                     // e^{-i delta} on the sub-step
-                    const R t = nr[q];
-                    nr[q] = fma(dl[q], ni[q], nr[q]);
-                    ni[q] = fma(-dl[q], t, ni[q]);
-                }
-            }
-        }
+        for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
         if (act) {
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
@@ -851,6 +966,131 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
     }
 }
 
+
+// Slice kernel for the tridiagonal layout (see k_sp_slice for what is computed).
+template <typename R>
+__global__ __launch_bounds__(256) void k_sp_slice_tri(SpArgs a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    int gw = blockIdx.x * WPB + (threadIdx.x >> 6);
+    gw = __builtin_amdgcn_readfirstlane(gw);
+    const int b = gw / a.waves_per_inst;
+    if (b >= a.B) return;
+    const int wi = gw - b * a.waves_per_inst;
+    const int d = a.d, LPI = (d + RPL - 1) / RPL;
+    const int p = lane / LPI, li = lane - p * LPI;
+    const int item = wi * a.P + p;
+    const bool valid = p < a.P && item < a.items_per_inst;
+    const int n = valid ? item : 0;
+    const int r0 = li * RPL;
+    const TaylorP tp = a.tp[b];
+    const int m = __builtin_amdgcn_readfirstlane(tp.m);
+    const int S = __builtin_amdgcn_readfirstlane(tp.S);
+    R dg[RPL], dl[RPL], Lc[RPL], Rc[RPL];
+    tri_coeffs(a, b, r0, valid, tp.tau_sub, dg, dl, Lc, Rc);
+    const int sn = a.s[n], L = a.s[n + 1] - sn;
+    const size_t pb = ((size_t)b * (a.N + 1)) * d;
+    const int left = (lane > 0 ? lane - 1 : 0) * 4, right = (lane < WAVE - 1 ? lane + 1 : lane) * 4;
+    R xr[RPL], xi[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = r0 + q;
+        xr[q] = xi[q] = 0;
+        if (valid && r < d) {
+            const dcx ph = a.phi[pb + (size_t)n * d + r];
+            xr[q] = (R)ph.re;
+            xi[q] = (R)ph.im;
+        }
+    }
+    // forward sweep from phi_n (phase-less factor of the step map)
+    const double* ub = a.u + (size_t)b * a.K;
+    double unext = ub[sn];
+    for (int jl = 0; jl < a.LMAX; ++jl) {
+        const bool act = valid && jl < L;
+        const R v = (R)unext;
+        unext = ub[sn + (jl + 1 < L ? jl + 1 : L - 1)];
+        R Ls[RPL], Rs[RPL], nr[RPL], ni[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            Ls[q] = v * Lc[q];
+            Rs[q] = v * Rc[q];
+            nr[q] = xr[q];
+            ni[q] = xi[q];
+        }
+        for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                xr[q] = nr[q];
+                xi[q] = ni[q];
+            }
+        }
+    }
+    // adjoint sweep from phi_{n+1}, reversal of the forward sweep, gradient, update
+    R cr[RPL], ci[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = r0 + q;
+        cr[q] = ci[q] = 0;
+        if (valid && r < d) {
+            const dcx ph = a.phi[pb + (size_t)(n + 1) * d + r];
+            cr[q] = (R)ph.re;
+            ci[q] = (R)ph.im;
+        }
+    }
+    const double theta = a.tau * a.shift[b] * (double)L;
+    const double cph = cos(theta), sph = sin(theta);   // e^{-i theta} = cph - i sph
+    const double beta_over_tau = ((double)a.K / (double)L) / a.tau;
+    const bool upd = a.update && (a.active == nullptr || a.active[b] != 0);
+    unext = ub[sn + (a.LMAX - 1 < L ? a.LMAX - 1 : L - 1)];
+    for (int jl = a.LMAX - 1; jl >= 0; --jl) {
+        const bool act = valid && jl < L;
+        const int j = sn + (jl < L ? jl : L - 1);
+        const double ud = unext;
+        const R v = (R)ud;
+        // step j-1 is updated only in the next pass of this loop
+        if (jl > 0) unext = ub[sn + (jl - 1 < L ? jl - 1 : L - 1)];
+        R Ls[RPL], Rs[RPL], ncr[RPL], nci[RPL], npr[RPL], npi[RPL], yr[RPL], yi[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            Ls[q] = v * Lc[q];
+            Rs[q] = v * Rc[q];
+            ncr[q] = cr[q];
+            nci[q] = ci[q];
+            npr[q] = xr[q];
+            npi[q] = xi[q];
+            yr[q] = yi[q] = 0;
+        }
+        for (int sub = 0; sub < S; ++sub)
+            tri_adj_substep(ncr, nci, npr, npi, yr, yi, dg, dl, Lc, Rc, Ls, Rs, v, left, right, m);
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                cr[q] = ncr[q];
+                ci[q] = nci[q];
+                xr[q] = npr[q];
+                xi[q] = npi[q];
+            }
+        }
+        // <y | psi_j> in FP64 (rows beyond d hold zeros)
+        double ore = 0.0, oim = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const double yre = (double)yr[q], yim = (double)yi[q];
+            const double qre = (double)xr[q], qim = (double)xi[q];
+            ore += fma(yre, qre, yim * qim);
+            oim += fma(yre, qim, -yim * qre);
+        }
+        ore = lanes_sum(ore, lane, li, LPI);
+        oim = lanes_sum(oim, lane, li, LPI);
+        if (act && li == 0) {
+            const double al = a.alpha ? a.alpha[j] : 0.0;
+            const double g = beta_over_tau * fma(cph, ore, sph * oim) - al * ud;
+            const size_t ui = (size_t)b * a.K + j;
+            if (a.grad) a.grad[ui] = g;
+            if (upd) a.u[ui] = fma(a.rho, g, ud);
+        }
+    }
+}
 
 #define ISM_SP_DISPATCH(KERNEL, R, X, VI, GRID, BLOCK, SHMEM, ST, ARGS)                            \
     switch (VI) {                                                                                \
@@ -945,6 +1185,21 @@ hipError_t sp_launch_assemble_tri(const SpArgs& a0, int precision, hipStream_t s
         hipLaunchKernelGGL(k_sp_assemble_tri<double>, grid, block, 0, st, a);
     else
         hipLaunchKernelGGL(k_sp_assemble_tri<float>, grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t sp_launch_slice_tri(const SpArgs& a0, int precision, hipStream_t st) {
+    SpArgs a = a0;
+    const int LPI = (a.d + RPL - 1) / RPL;
+    a.P = WAVE / LPI;
+    a.items_per_inst = a.N;
+    a.waves_per_inst = (a.items_per_inst + a.P - 1) / a.P;
+    const long waves = (long)a.B * a.waves_per_inst;
+    const dim3 grid((unsigned)((waves + WPB - 1) / WPB)), block(WAVE * WPB);
+    if (precision == ISM_FP64)
+        hipLaunchKernelGGL(k_sp_slice_tri<double>, grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL(k_sp_slice_tri<float>, grid, block, 0, st, a);
     return hipGetLastError();
 }
 
