@@ -36,9 +36,9 @@ PEAK_ALU = 78.6e12       # non-packed FP32 and FP64 vector FMA rate: 256 CU x 64
 # change to them the field is reported as null until the counters are taken again.
 TRAFFIC_SOURCES = ["paper_1603_01237_amd/csrc/k_sparse.hip",
                    "paper_1603_01237_amd/csrc/ism_internal.h"]
-TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 54511.9, "write_kib": 112896.0,
+TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 32429.3, "write_kib": 113344.0,
            "copy_fetch_per_kib": 0.50001, "copy_write_per_kib": 1.0,
-           "sha256": "cbb4edfda02e145587a23cdd37c888e0d1df44f959572598e33455f3aadc4a5e"}
+           "sha256": "e422eca4d09585d7750ffa401a89520b43e7e12f84ab1dc9e25eb2c1ba4ce622"}
 COPY_BYTES = 1 << 30
 
 
