@@ -293,16 +293,35 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
 
 // w_ab = i^{a+b} (-1)^b / ((a+b+1) a! b!) as a real magnitude; the phase i^{a+b}(-1)^b is
 // applied in the kernel.
-__constant__ double WAB[MMAX_G + 1][MMAX_G + 1];
+struct WabTable {
+    double v[MMAX_G + 1][MMAX_G + 1];
+};
+// |w_ab| = 1 / ((a+b+1) a! b!), evaluated by the compiler so that the unrolled series
+// take the weights as instruction constants
+constexpr WabTable make_wab() {
+    WabTable t{};
+    double f[2 * MMAX_G + 2] = {};
+    f[0] = 1.0;
+    for (int i = 1; i < 2 * MMAX_G + 2; ++i) f[i] = f[i - 1] * i;
+    for (int a = 0; a <= MMAX_G; ++a)
+        for (int b = 0; a + b <= MMAX_G; ++b) t.v[a][b] = 1.0 / ((a + b + 1) * f[a] * f[b]);
+    return t;
+}
+__device__ constexpr WabTable kWab = make_wab();
 
 // Per (step, block of CBW columns): partial sums over rows and columns of
 // Im <y_k| Hhat_c |x_k> for every control c, in FP64.  MK bounds the Krylov order.
 template <typename R, int MK, int WT>
 __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
                                                    int ldxy, double* gpart, int ncb) {
+    // LDS: per-row gradient accumulators of every control; Krylov vectors (tau H')^b x,
+    // b = 0..MK, as re/im planes; a double buffer for the Krylov vectors of y; the
+    // per-wavefront partial sums of the final reduction.
     extern __shared__ unsigned char smem_raw[];
-    R* kv = reinterpret_cast<R*>(smem_raw);                    // 2 (MK+1) dp
-    __shared__ double red[256];
+    double* gacc = reinterpret_cast<double*>(smem_raw);          // C dp
+    R* kv = reinterpret_cast<R*>(gacc + (size_t)gg.C * gg.dp);  // 2 (MK+1) dp
+    R* yb = kv + 2 * (MK + 1) * gg.dp;                          // 2 x 2 dp
+    __shared__ double red[4][CMAX_G];
     const int j = blockIdx.x, cb = blockIdx.y, r = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
     const double* uj = gg.u + (size_t)j * gg.C;
@@ -341,111 +360,105 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
         hvi[w] = (R)(gg.tau * hi);
         hcol[w] = cc;
     }
-    double accg[CMAX_G];
-#pragma unroll
-    for (int q = 0; q < CMAX_G; ++q) accg[q] = 0.0;
-    R rtr[MK + 1], rti[MK + 1], ptr_[MK + 1], pti[MK + 1];
+    for (int q = 0; q < gg.C; ++q) gacc[q * dp + r] = 0.0;     // own slots only
     for (int kk = 0; kk < CBW; ++kk) {
         const int k = cb * CBW + kk;
-        if (k >= d) break;
-        // column k of X_j and Y_j
+        if (k >= d) break;                    // uniform over the workgroup
+        // column k of X_j (x) and Y_j (y)
         const long long ox = (long long)j * xy_plane * 2 + (long long)r * ldxy + k;
-        rtr[0] = r < d ? XY[ox] : R(0);
-        rti[0] = r < d ? XY[ox + xy_plane] : R(0);
-        ptr_[0] = r < d ? XY[ox + dp] : R(0);
-        pti[0] = r < d ? XY[ox + dp + xy_plane] : R(0);
-        // Krylov vectors (tau H')^a of both columns
-#pragma unroll
-        for (int a = 1; a <= MK; ++a) {
-            if (a > m) break;
-            kv[r] = rtr[a - 1];
-            kv[dp + r] = rti[a - 1];
-            kv[2 * dp + r] = ptr_[a - 1];
-            kv[3 * dp + r] = pti[a - 1];
-            __syncthreads();
-            R xr = 0, xi = 0, yr = 0, yi = 0;
-#pragma unroll
-            for (int w = 0; w < WT; ++w) {
-                const int cc = hcol[w];
-                const R ur = kv[cc], ui = kv[dp + cc], vr = kv[2 * dp + cc], vi = kv[3 * dp + cc];
-                xr = fma(hvr[w], ur, fma(-hvi[w], ui, xr));
-                xi = fma(hvr[w], ui, fma(hvi[w], ur, xi));
-                yr = fma(hvr[w], vr, fma(-hvi[w], vi, yr));
-                yi = fma(hvr[w], vi, fma(hvi[w], vr, yi));
-            }
-            rtr[a] = xr;
-            rti[a] = xi;
-            ptr_[a] = yr;
-            pti[a] = yi;
-            __syncthreads();
-        }
-        // Krylov vectors of x into LDS
-#pragma unroll
-        for (int b = 0; b <= MK; ++b) {
-            if (b > m) break;
-            kv[(2 * b) * dp + r] = rtr[b];
-            kv[(2 * b + 1) * dp + r] = rti[b];
-        }
-        __syncthreads();
-        // t_b = sum_a conj(w_ab) p_a with conj(w_ab) = (-i)^{a+b} (-1)^b |w_ab|, then per
-        // control the imaginary part of sum_b conj(t_b) (H_c r_b)
+        R xr = r < d ? XY[ox] : R(0), xi = r < d ? XY[ox + xy_plane] : R(0);
+        R yr = r < d ? XY[ox + dp] : R(0), yi = r < d ? XY[ox + dp + xy_plane] : R(0);
+        __syncthreads();                      // the previous column's readers of kv are done
+        kv[r] = xr;
+        kv[dp + r] = xi;
+        yb[r] = yr;
+        yb[dp + r] = yi;
+        // t_b = sum_a conj(w_ab) p_a, p_a = (tau H')^a y, with
+        // conj(w_ab) = (-i)^{a+b} (-1)^b |w_ab|, accumulated as the p_a are produced
         R ttr[MK + 1], tti[MK + 1];
 #pragma unroll
-        for (int b = 0; b <= MK; ++b) {
-            R sr = 0, si = 0;
+        for (int b = 0; b <= MK; ++b) ttr[b] = tti[b] = 0;
 #pragma unroll
-            for (int a = 0; a + b <= MK; ++a) {
-                if (a + b > m) break;
-                R wr = (R)WAB[a][b];
-                if (b & 1) wr = -wr;
-                const R pr = ptr_[a], pim = pti[a];
-                const int ph = (a + b) & 3;
-                const R qr = ph == 0 ? pr : ph == 1 ? pim : ph == 2 ? -pr : -pim;
-                const R qi = ph == 0 ? pim : ph == 1 ? -pr : ph == 2 ? -pim : pr;
-                sr = fma(wr, qr, sr);
-                si = fma(wr, qi, si);
+        for (int a = 0; a <= MK; ++a) {
+            if (a > 0) {
+                // Krylov step a of x and y (every thread reaches the barrier every time)
+                __syncthreads();
+                const R* xs = kv + 2 * (a - 1) * dp;
+                const R* ys = yb + 2 * ((a - 1) & 1) * dp;
+                R nxr = 0, nxi = 0, nyr = 0, nyi = 0;
+                if (a <= m) {
+#pragma unroll
+                    for (int w = 0; w < WT; ++w) {
+                        const int cc = hcol[w];
+                        const R ur = xs[cc], ui = xs[dp + cc], vr = ys[cc], vi = ys[dp + cc];
+                        nxr = fma(hvr[w], ur, fma(-hvi[w], ui, nxr));
+                        nxi = fma(hvr[w], ui, fma(hvi[w], ur, nxi));
+                        nyr = fma(hvr[w], vr, fma(-hvi[w], vi, nyr));
+                        nyi = fma(hvr[w], vi, fma(hvi[w], vr, nyi));
+                    }
+                    kv[2 * a * dp + r] = nxr;
+                    kv[(2 * a + 1) * dp + r] = nxi;
+                    yb[2 * (a & 1) * dp + r] = nyr;
+                    yb[(2 * (a & 1) + 1) * dp + r] = nyi;
+                }
+                yr = nyr;
+                yi = nyi;
             }
-            ttr[b] = sr;
-            tti[b] = si;
-        }
-        if (r < d) {
+            if (a <= m) {
 #pragma unroll
-            for (int q = 0; q < CMAX_G; ++q) {
-                if (q >= gg.C) break;
+                for (int b = 0; b + a <= MK; ++b) {
+                    if (a + b <= m) {
+                        R wr = (R)kWab.v[a][b];
+                        if (b & 1) wr = -wr;
+                        const int ph = (a + b) & 3;
+                        const R qr = ph == 0 ? yr : ph == 1 ? yi : ph == 2 ? -yr : -yi;
+                        const R qi = ph == 0 ? yi : ph == 1 ? -yr : ph == 2 ? -yi : yr;
+                        ttr[b] = fma(wr, qr, ttr[b]);
+                        tti[b] = fma(wr, qi, tti[b]);
+                    }
+                }
+            }
+        }
+        __syncthreads();                      // all Krylov vectors of x are in kv
+        // per control: Im of sum_b conj(t_b) (H_c r_b)_row
+        if (r < d) {
+            for (int q = 0; q < gg.C; ++q) {
                 double sacc = 0.0;
                 for (int wc = 0; wc < gg.WCc; ++wc) {
                     const size_t ci = ((size_t)q * d + r) * gg.WCc + wc;
                     const int cc = gg.ccol[ci];
                     const dcx hv = gg.cval[ci];
+                    // s = sum_b conj(t_b) r_b(cc) in the path precision, then
+                    // Im(s h) = Im(conj(t_b) h r_b) summed, accumulated in FP64
+                    R sr = 0, si = 0;
 #pragma unroll
                     for (int b = 0; b <= MK; ++b) {
-                        if (b > m) break;
-                        const double xr = (double)kv[(2 * b) * dp + cc];
-                        const double xi = (double)kv[(2 * b + 1) * dp + cc];
-                        const double yr = hv.re * xr - hv.im * xi, yi = hv.re * xi + hv.im * xr;
-                        sacc += (double)ttr[b] * yi - (double)tti[b] * yr;   // Im(conj(t_b) y)
+                        if (b <= m) {
+                            const R rr = kv[(2 * b) * dp + cc], ri = kv[(2 * b + 1) * dp + cc];
+                            sr = fma(ttr[b], rr, fma(tti[b], ri, sr));
+                            si = fma(ttr[b], ri, fma(-tti[b], rr, si));
+                        }
                     }
+                    sacc += hv.re * (double)si + hv.im * (double)sr;
                 }
-                accg[q] += sacc;
+                gacc[q * dp + r] += sacc;
             }
         }
-        __syncthreads();
     }
-    // block reduction over rows (deterministic tree)
-#pragma unroll
-    for (int q = 0; q < CMAX_G; ++q) {
-        if (q >= gg.C) break;
-        red[r] = r < d ? accg[q] : 0.0;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (r < w) red[r] += red[r + w];
-            __syncthreads();
-        }
-        if (r == 0) gpart[((size_t)j * ncb + cb) * gg.C + q] = red[0];
-        __syncthreads();
+    // reduction over rows: wavefront tree, then the four partials in order
+    const int wv = r >> 6, lane = r & 63;
+    for (int q = 0; q < gg.C; ++q) {
+        double v = r < d ? gacc[q * dp + r] : 0.0;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (r < gg.C) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][r];
+        gpart[((size_t)j * ncb + cb) * gg.C + r] = s;
     }
 }
-
 // g_{j,c} = beta_n (1/d) sum_cb gpart - alpha_j u_{j,c}; update or write the gradient.
 __global__ void k_gate_grad_finish(const double* gpart, int ncb, int K, int N, int C, int d,
                                    const int* s, double* u, const double* alpha, double* grad,
