@@ -298,13 +298,16 @@ __device__ void fwd_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
                         dcx* psi_out, bool cont) {
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
+    const double* ub = A.u + (size_t)b * A.K;
+    double un = ub[j0];
     for (int j = j0; j < j1; ++j) {
         Cx<R>* tj = traj_b + (size_t)j * NN;
 #pragma unroll
         for (int i = 0; i < 16; ++i) tj[t + T * i] = down<R>(x[i]);
         const bool last = j == j1 - 1;
         if (last && !psi_out && !cont) return;
-        const double u = A.u[(size_t)b * A.K + j];
+        const double u = un;
+        if (!last) un = ub[j + 1];                        // next step's control, ahead of use
 #pragma unroll
         for (int i = 0; i < 16; ++i) x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, x[i]));
         if (!last) {
@@ -328,13 +331,33 @@ __device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
     const Cd* conjKh = reinterpret_cast<const Cd*>(A.Kh);
+    double* ub = A.u + (size_t)b * A.K;
+    // u_j of the next step down is requested one step ahead (u_{j-1} is read before this
+    // loop updates it); so is a_j in the FP32 path, whose copy costs half the registers
+    constexpr bool kAhead = sizeof(R) == 4;
+    Cx<R> an[16];
+    double un = ub[j1 - 1];
+    if (kAhead) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) an[i] = traj_b[(size_t)(j1 - 1) * NN + t + T * i];
+    }
     for (int j = j1 - 1; j >= j0; --j) {
-        const Cx<R>* tj = traj_b + (size_t)j * NN;
-        const double u = A.u[(size_t)b * A.K + j];
+        const double u = un;
+        Cd av[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            av[i] = up<R>(kAhead ? an[i] : traj_b[(size_t)j * NN + t + T * i]);
+        if (j > j0) {
+            un = ub[j - 1];
+            if (kAhead) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) an[i] = traj_b[(size_t)(j - 1) * NN + t + T * i];
+            }
+        }
         double part = 0.0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const Cd a = up<R>(tj[t + T * i]);
+            const Cd a = av[i];
             const Cd e = phase<R>(A, v0[i], v1[i], u, a);
             if (grad_on) {
                 const Cd bb = cmul(a, e);
@@ -350,7 +373,7 @@ __device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
             if (t == 0) {
                 const size_t ui = (size_t)b * A.K + j;
                 if (A.grad) A.grad[ui] = gj;
-                if (upd) A.u[ui] = fma(A.rho, gj, u);
+                if (upd) ub[j] = fma(A.rho, gj, u);
                 if (!(fabs(gj) < 1e300)) atomicOr(&A.flags[0], 1);
             }
         }
