@@ -72,13 +72,14 @@ def copy_calibration():
                                            "write_bytes": COPY_BYTES, "launches": 3}}), flush=True)
 
 
-def serving_sample(n_req, iters_per_round=10, max_running=64):
+def serving_sample(n_req, iters_per_round=5, max_running=16):
     """Replay of the first n_req requests of the seeded 200 req/s serving trace at their
     arrival times (FP32 mixed; stop at F >= 0.99 or 200 iterations)."""
     import problems
     from paper_1603_01237_amd import Server
     from paper_1603_01237_amd.serve import latency_summary, replay
     trace = problems.serving_trace()[:n_req]
+    types = [f"{r['type']}{r['size']}" for r in trace]
     items = [(r["arrival"] - trace[0]["arrival"], problems.request_problem(r),
               dict(max_iter=200, rho=problems.SERVE_RHO[r["type"]], fid_stop=0.99,
                    precision="fp32")) for r in trace]
@@ -87,6 +88,10 @@ def serving_sample(n_req, iters_per_round=10, max_running=64):
                             log=lambda m: print(m, file=sys.stderr, flush=True))
         st = s.stats()
     out = latency_summary(recs, wall)
+    by_type = {}
+    for t, r in zip(types, recs):
+        by_type.setdefault(t, []).append(round(r["latency_s"], 3))
+    out["latency_s_by_type"] = by_type
     out.update({"busy_frac": st["busy_s"] / wall if wall > 0 else None,
                 "peak_device_GB": st["bytes_peak"] / 1e9,
                 "mean_iters": float(sum(r["iters"] for r in recs) / max(len(recs), 1)),
@@ -247,7 +252,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the two-spin, gate and condensate workloads")
-    ap.add_argument("--serve", type=int, default=0,
+    ap.add_argument("--serve", type=int, default=16,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the streaming kernel that scales the HBM byte counters")
@@ -257,9 +262,9 @@ def main():
               "instances is a design (see the design notes), not part of this build",
               file=sys.stderr)
         sys.exit(2)
-    # more hardware queues than HIP's default 4, so that the streams of concurrently
+    # 16 hardware queues instead of HIP's default 4, so that the streams of concurrently
     # served requests run side by side (set before the HIP runtime initialises)
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
     import torch
     import problems
     torch.cuda.init()
