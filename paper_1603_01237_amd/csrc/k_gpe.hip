@@ -117,21 +117,37 @@ __device__ __forceinline__ void dft16(Cd (&x)[16]) {
     for (int i = 0; i < 16; ++i) x[i] = y[i];
 }
 
-// LDS carve-up of a workgroup
+// LDS carve-up of a workgroup.  Complex arrays are split into real and imaginary planes of
+// doubles: the exchange accesses are then 8-byte words on consecutive (padded) addresses,
+// which the LDS serves without bank conflicts (interleaved pairs put lanes 16 bytes apart).
 struct Lds {
-    Cd* st;            // n + n/16: padded FFT exchange buffer
-    Cd* kf;            // n: e^{-i tau k^2/2} / n
-    Cd* tab;           // 768: [0,256) W_256^{r k}; [256,512) W_n^{16 r k}; [512,768) W_n^{r k}
+    double* sr;        // n + n/16: padded FFT exchange buffer, real plane
+    double* si;        //           imaginary plane
+    double* kr;        // n: e^{-i tau k^2/2} / n
+    double* ki;
+    double* tr;        // 768: [0,256) W_256^{r k}; [256,512) W_n^{16 r k}; [512,768) W_n^{r k}
+    double* ti;
     double* red;       // 16
+    __device__ __forceinline__ Cd tab(int i) const { return Cd{tr[i], ti[i]}; }
+    __device__ __forceinline__ Cd kf(int i) const { return Cd{kr[i], ki[i]}; }
+    __device__ __forceinline__ Cd ld(int i) const { return Cd{sr[i], si[i]}; }
+    __device__ __forceinline__ void st(int i, Cd v) const {
+        sr[i] = v.re;
+        si[i] = v.im;
+    }
 };
 
 template <int NN>
 __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
+    constexpr int PN = NN + NN / 16;
     Lds L;
-    L.st = reinterpret_cast<Cd*>(raw);
-    L.kf = L.st + NN + NN / 16;
-    L.tab = L.kf + NN;
-    L.red = reinterpret_cast<double*>(L.tab + 768);
+    L.sr = reinterpret_cast<double*>(raw);
+    L.si = L.sr + PN;
+    L.kr = L.si + PN;
+    L.ki = L.kr + NN;
+    L.tr = L.ki + NN;
+    L.ti = L.tr + 768;
+    L.red = L.ti + 768;
     return L;
 }
 
@@ -143,30 +159,30 @@ __device__ void fft(Cd (&x)[16], const Lds& L) {
     const int t = threadIdx.x;
     // pass 1: radix 16, sub-transform size 1 (no twiddles)
     dft16<SIGN>(x);
-    __syncthreads();                          // earlier readers of st are done
+    __syncthreads();                          // earlier readers of the buffer are done
 #pragma unroll
-    for (int c = 0; c < 16; ++c) L.st[pad(16 * t + c)] = x[c];
+    for (int c = 0; c < 16; ++c) L.st(pad(16 * t + c), x[c]);
     __syncthreads();
     // pass 2: radix 16, sub-transform size 16
 #pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = L.st[pad(t + T * r)];
+    for (int r = 0; r < 16; ++r) x[r] = L.ld(pad(t + T * r));
     const int k = t & 15;
 #pragma unroll
-    for (int r = 1; r < 16; ++r) x[r] = cmul_s<SIGN>(x[r], L.tab[r * 16 + k]);
+    for (int r = 1; r < 16; ++r) x[r] = cmul_s<SIGN>(x[r], L.tab(r * 16 + k));
     dft16<SIGN>(x);
     __syncthreads();                          // every thread has read its inputs
     const int base = (t >> 4) * 256 + k;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) L.st[pad(base + 16 * c)] = x[c];
+    for (int c = 0; c < 16; ++c) L.st(pad(base + 16 * c), x[c]);
     __syncthreads();
     // pass 3: sub-transform size 256; twiddle W_n^{r k} = W_n^{16 r (k>>4)} W_n^{r (k&15)}
     if constexpr (NN == 4096) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = L.st[pad(t + 256 * r)];
+        for (int r = 0; r < 16; ++r) x[r] = L.ld(pad(t + 256 * r));
         const int kh = t >> 4, kl = t & 15;
 #pragma unroll
         for (int r = 1; r < 16; ++r)
-            x[r] = cmul_s<SIGN>(x[r], cmul(L.tab[256 + r * 16 + kh], L.tab[512 + r * 16 + kl]));
+            x[r] = cmul_s<SIGN>(x[r], cmul(L.tab(256 + r * 16 + kh), L.tab(512 + r * 16 + kl)));
         dft16<SIGN>(x);
     } else {
         static_assert(NN == 1024, "grid sizes 1024 and 4096");
@@ -174,11 +190,11 @@ __device__ void fft(Cd (&x)[16], const Lds& L) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int j = t + 64 * s, kh = j >> 4, kl = j & 15;
-            Cd v0 = L.st[pad(j)], v1 = L.st[pad(j + 256)], v2 = L.st[pad(j + 512)],
-               v3 = L.st[pad(j + 768)];
-            v1 = cmul_s<SIGN>(v1, cmul(L.tab[256 + 16 + kh], L.tab[512 + 16 + kl]));
-            v2 = cmul_s<SIGN>(v2, cmul(L.tab[256 + 32 + kh], L.tab[512 + 32 + kl]));
-            v3 = cmul_s<SIGN>(v3, cmul(L.tab[256 + 48 + kh], L.tab[512 + 48 + kl]));
+            Cd v0 = L.ld(pad(j)), v1 = L.ld(pad(j + 256)), v2 = L.ld(pad(j + 512)),
+               v3 = L.ld(pad(j + 768));
+            v1 = cmul_s<SIGN>(v1, cmul(L.tab(256 + 16 + kh), L.tab(512 + 16 + kl)));
+            v2 = cmul_s<SIGN>(v2, cmul(L.tab(256 + 32 + kh), L.tab(512 + 32 + kl)));
+            v3 = cmul_s<SIGN>(v3, cmul(L.tab(256 + 48 + kh), L.tab(512 + 48 + kl)));
             dft4<SIGN>(v0, v1, v2, v3);
             y[s] = v0;
             y[s + 4] = v1;
@@ -223,8 +239,14 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, double (&v
                                       double (&v1)[16]) {
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
-    for (int i = t; i < NN; i += T) L.kf[i] = Cd{A.Kf[i].re, A.Kf[i].im};
-    for (int i = t; i < 768; i += T) L.tab[i] = Cd{A.tab[i].re, A.tab[i].im};
+    for (int i = t; i < NN; i += T) {
+        L.kr[i] = A.Kf[i].re;
+        L.ki[i] = A.Kf[i].im;
+    }
+    for (int i = t; i < 768; i += T) {
+        L.tr[i] = A.tab[i].re;
+        L.ti[i] = A.tab[i].im;
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         v0[i] = A.V0[t + T * i];
@@ -248,15 +270,16 @@ __device__ __forceinline__ double block_sum(double v, const Lds& L) {
     return s;
 }
 
-// x <- F^-1 diag(k) F x with k read at the owned frequencies from LDS or global memory;
-// CONJ uses conj(k) (adjoint kicks)
+// x <- F^-1 diag(k) F x, k at the owned frequencies: the fused kinetic factor from LDS
+// (kt == nullptr) or a table in global memory; CONJ uses conj(k) (adjoint kicks)
 template <int NN, bool CONJ>
 __device__ __forceinline__ void kick(Cd (&x)[16], const Lds& L, const Cd* kt) {
     constexpr int T = NN / 16;
     fft<NN, -1>(x, L);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const Cd k = kt[threadIdx.x + T * i];
+        const int m = threadIdx.x + T * i;
+        const Cd k = kt ? kt[m] : L.kf(m);
         x[i] = CONJ ? cmulc(x[i], k) : cmul(x[i], k);
     }
     fft<NN, 1>(x, L);
@@ -311,7 +334,7 @@ __device__ void fwd_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
 #pragma unroll
         for (int i = 0; i < 16; ++i) x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, x[i]));
         if (!last) {
-            kick<NN, false>(x, L, L.kf);
+            kick<NN, false>(x, L, nullptr);
         } else {
             kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
             if (psi_out) store_state<NN>(psi_out, x);
@@ -378,7 +401,7 @@ __device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
             }
         }
         if (j > j0) {
-            kick<NN, true>(x, L, L.kf);
+            kick<NN, true>(x, L, nullptr);
         } else if (final_kick > 0) {
             kick<NN, true>(x, L, conjKh);
             if (nu_out) store_state<NN>(nu_out, x);
