@@ -591,41 +591,77 @@ __global__ __launch_bounds__(256) void k_sp_params(SpArgs a, const double* h0nor
 // --------------------------------------------------------------------------------
 // boundary rebuild: 2N products with the assembled slice propagators (FP64)
 // --------------------------------------------------------------------------------
-template <typename RM>
+template <typename RM, bool STAGED>
 __global__ __launch_bounds__(512) void k_sp_boundary(BndArgs a) {
+    // LDS: the two current vectors, the reduction slots and (STAGED, small d) a double buffer
+    // holding the forward and adjoint slice propagators of the current product while those
+    // of the next one are on their way from HBM
     extern __shared__ double smem[];
     dcx* xs = reinterpret_cast<dcx*>(smem);             // 2*d
     double* red = smem + 4 * a.d;                        // blockDim
+    const int d = a.d, N = a.N, dd = d * d;
+    RM* ms = reinterpret_cast<RM*>(red + blockDim.x);    // 2 buffers x 2 matrices x dd pairs
     const int b = blockIdx.x, tid = threadIdx.x;
     const int DP = blockDim.x / 2;
     const int grp = tid / DP, r = tid - grp * DP;
-    const int d = a.d, N = a.N;
     const double sh = a.shift[b];
     const size_t pb = (size_t)b * (N + 1) * d;
-    const RM* Mb = reinterpret_cast<const RM*>(a.M) + (size_t)b * N * d * d * 2;
+    const RM* Mb = reinterpret_cast<const RM*>(a.M) + (size_t)b * N * dd * 2;
+    // this thread's share of the 2 dd complex entries of one product's pair of propagators
+    constexpr int PER = 4;
+    RM pre[PER][2];
+    auto fetch = [&](int it) {
+        if (!STAGED) return;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * (int)blockDim.x;
+            if (idx < 2 * dd) {
+                const int which = idx >= dd, e = idx - which * dd;
+                const int n = which == 0 ? it : N - 1 - it;
+                pre[q][0] = Mb[((size_t)n * dd + e) * 2];
+                pre[q][1] = Mb[((size_t)n * dd + e) * 2 + 1];
+            }
+        }
+    };
+    auto stage = [&](int it) {
+        if (!STAGED) return;
+        RM* dst = ms + (size_t)(it & 1) * 4 * dd;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * (int)blockDim.x;
+            if (idx < 2 * dd) {
+                dst[idx * 2] = pre[q][0];
+                dst[idx * 2 + 1] = pre[q][1];
+            }
+        }
+    };
     if (r < d) {
         const dcx v = grp == 0 ? a.psi0[r] : a.target[r];
         xs[grp * d + r] = v;
         if (grp == 0) a.Psi[pb + r] = v;
         else a.Lam[pb + (size_t)N * d + r] = v;
     }
-    __syncthreads();
+    fetch(0);
     for (int it = 0; it < N; ++it) {
+        stage(it);
+        __syncthreads();                                 // staged matrices and xs visible
+        if (it + 1 < N) fetch(it + 1);                  // next pair, consumed a step later
+        const RM* Mf = STAGED ? ms + (size_t)(it & 1) * 4 * dd : Mb + (size_t)it * dd * 2;
+        const RM* Ma = STAGED ? Mf + 2 * dd : Mb + (size_t)(N - 1 - it) * dd * 2;
         dcx y = {0.0, 0.0};
         const int n = grp == 0 ? it : N - 1 - it;
         if (r < d) {
-            const RM* Mn = Mb + (size_t)n * d * d * 2;
             double yr = 0.0, yi = 0.0;
             if (grp == 0) {
                 for (int c = 0; c < d; ++c) {         // (M' x)_r, M' column-major
-                    const double mr = (double)Mn[(c * d + r) * 2], mi = (double)Mn[(c * d + r) * 2 + 1];
+                    const double mr = (double)Mf[(c * d + r) * 2], mi = (double)Mf[(c * d + r) * 2 + 1];
                     const dcx x = xs[c];
                     yr = fma(mr, x.re, fma(-mi, x.im, yr));
                     yi = fma(mr, x.im, fma(mi, x.re, yi));
                 }
             } else {
                 for (int c = 0; c < d; ++c) {         // (M'^+ x)_r = sum_c conj(M'_{c r}) x_c
-                    const double mr = (double)Mn[(r * d + c) * 2], mi = (double)Mn[(r * d + c) * 2 + 1];
+                    const double mr = (double)Ma[(r * d + c) * 2], mi = (double)Ma[(r * d + c) * 2 + 1];
                     const dcx x = xs[d + c];
                     yr = fma(mr, x.re, fma(mi, x.im, yr));
                     yi = fma(mr, x.im, fma(-mi, x.re, yi));
@@ -637,14 +673,14 @@ __global__ __launch_bounds__(512) void k_sp_boundary(BndArgs a) {
             y.re = c0 * yr - s0 * yi;
             y.im = c0 * yi + s0 * yr;
         }
-        __syncthreads();
+        __syncthreads();                                 // every product has read xs
         if (r < d) {
             xs[grp * d + r] = y;
             if (grp == 0) a.Psi[pb + (size_t)(it + 1) * d + r] = y;
             else a.Lam[pb + (size_t)n * d + r] = y;
         }
-        __syncthreads();
     }
+    __syncthreads();
     // intermediate states (Eq. (cible)), t_n / T = s_n / K
     for (int idx = tid; idx < (N + 1) * d; idx += blockDim.x) {
         const int n = idx / d;
@@ -1106,9 +1142,9 @@ __global__ __launch_bounds__(256) void k_sp_slice_tri(SpArgs a) {
         default: return hipErrorInvalidValue;                                                    \
     }
 
-template <typename Kern>
+template <typename Kern, typename Args>
 static void launch_with_shm(Kern kf, dim3 grid, dim3 block, size_t shm, hipStream_t st,
-                            const SpArgs& a) {
+                            const Args& a) {
     if (shm > 65536)
         hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL(kf, grid, block, shm, st, a);
@@ -1216,13 +1252,21 @@ hipError_t sp_launch_slice(const SpArgs& a, int vi, int precision, hipStream_t s
 }
 
 hipError_t sp_launch_boundary(const BndArgs& a, hipStream_t st) {
-    int DP = ((a.d + 63) / 64) * 64;
+    // staged (double-buffered propagators in LDS) when one product's pair of propagators,
+    // 2 d^2 entries, fits 4 per thread of a 512-thread workgroup
+    const bool staged = 2 * a.d * a.d <= 4 * 512;
+    const int DP = staged ? 256 : ((a.d + 63) / 64) * 64;
     const int threads = 2 * DP;
-    const size_t shmem = (size_t)4 * a.d * sizeof(double) + (size_t)threads * sizeof(double);
-    if (a.m_fp32)
-        hipLaunchKernelGGL(k_sp_boundary<float>, dim3(a.B), dim3(threads), shmem, st, a);
-    else
-        hipLaunchKernelGGL(k_sp_boundary<double>, dim3(a.B), dim3(threads), shmem, st, a);
+    const size_t rs = a.m_fp32 ? sizeof(float) : sizeof(double);
+    const size_t shmem = (size_t)4 * a.d * sizeof(double) + (size_t)threads * sizeof(double) +
+                         (staged ? (size_t)8 * a.d * a.d * rs : 0);
+    if (a.m_fp32) {
+        if (staged) launch_with_shm(k_sp_boundary<float, true>, dim3(a.B), dim3(threads), shmem, st, a);
+        else launch_with_shm(k_sp_boundary<float, false>, dim3(a.B), dim3(threads), shmem, st, a);
+    } else {
+        if (staged) launch_with_shm(k_sp_boundary<double, true>, dim3(a.B), dim3(threads), shmem, st, a);
+        else launch_with_shm(k_sp_boundary<double, false>, dim3(a.B), dim3(threads), shmem, st, a);
+    }
     return hipGetLastError();
 }
 

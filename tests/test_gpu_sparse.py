@@ -49,6 +49,11 @@ CASES = [
     ("spin2_K25_N1", lambda: problems.spin2(K=25, N=1)),
     ("rotor_B3_K90_N7", lambda: problems.rotor(batch=3, K=90, N=7, T=0.5)),
     ("rotor_j40_B2_K40_N6", lambda: problems.rotor(batch=2, jmax=40, K=40, N=6, T=0.1)),
+    # three-rows-per-lane layout: padded last lane (d=11), 32 items per wavefront (d=5),
+    # one step per slice (N = K), slices straddling wavefronts (d=21, N=13)
+    ("rotor_j10_B2_K50_N5_pad", lambda: problems.rotor(batch=2, jmax=10, K=50, N=5, T=0.2)),
+    ("rotor_j4_B3_K24_N24_NeqK", lambda: problems.rotor(batch=3, jmax=4, K=24, N=24, T=0.3)),
+    ("rotor_B2_K65_N13_straddle", lambda: problems.rotor(batch=2, K=65, N=13, T=0.3)),
     ("chain4_state_K21_N4", lambda: _chain_random(11, n=4, T=0.4, K=21, N=4)),
     ("chain7_state_K12_N3_block", lambda: _chain_random(12, n=7, T=0.3, K=12, N=3)),
     ("chain8_state_K10_N4_block", lambda: _chain_random(13, n=8, T=0.3, K=10, N=4)),
