@@ -153,9 +153,21 @@ def gpe_sweep_flops(prob):
     return 2.0 * prob.K * 2 * 5 * prob.n * math.log2(prob.n) * prob.batch
 
 
-def other_workloads(stream, iters_gate=2, iters_gpe=2):
+def other_workloads(stream, iters_gate=2, iters_gpe=2, which=("spins", "gate", "gpe")):
     """The paper's other benchmark shapes: the two-spin solve (latency), gate synthesis
     on MFMA and the condensate (sequential FFT sweeps)."""
+    import problems
+    out = {}
+    if "spins" in which:
+        out.update(_spins_workload(stream))
+    if "gate" in which:
+        out.update(_gate_workload(stream, iters_gate))
+    if "gpe" in which:
+        out.update(_gpe_workload(stream, iters_gpe))
+    return out
+
+
+def _spins_workload(stream):
     import problems
     out = {}
     p0 = problems.spin2()
@@ -165,6 +177,12 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2):
         "solve_ms": {k: v["seconds"] * 1e3 for k, v in r.items()},
         "useful_steps_per_s": {k: 2 * p0.K * p0.iters / v["seconds"] for k, v in r.items()},
         "final_F": {k: v["F_mean"] for k, v in r.items()}}
+    return out
+
+
+def _gate_workload(stream, iters_gate):
+    import problems
+    out = {}
     pg = problems.spin_chain_gate()
     r = {prec: run_gpu(prec, pg, iters_gate, 1, stream) for prec in ("fp32", "fp64")}
     dp = pg.d
@@ -181,6 +199,12 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2):
                                    "achieved": ach / 1e12, "peak": PEAK_MFMA[prec] / 1e12,
                                    "unit": "TFLOP/s", "frac": ach / PEAK_MFMA[prec]}
     out["gate_d256"] = ent
+    return out
+
+
+def _gpe_workload(stream, iters_gpe):
+    import problems
+    out = {}
     pe = problems.gpe()
     r = {prec: run_gpu(prec, pe, iters_gpe, 1, stream) for prec in ("fp32", "fp64")}
     ent = {"workload": f"condensate, n={pe.n}, K={pe.K}, N={pe.N}, g={pe.g}",
@@ -254,6 +278,8 @@ def main():
                     help="skip the two-spin, gate and condensate workloads")
     ap.add_argument("--serve", type=int, default=16,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
+    ap.add_argument("--only", choices=["spins", "gate", "gpe"],
+                    help="run only this secondary workload and print its figures (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the streaming kernel that scales the HBM byte counters")
     args = ap.parse_args()
@@ -270,6 +296,10 @@ def main():
     torch.cuda.init()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only:
+        stream = torch.cuda.current_stream().cuda_stream
+        print(json.dumps({"workloads": other_workloads(stream, which=(args.only,))}), flush=True)
         return
     stream = torch.cuda.current_stream().cuda_stream
     prob = problems.rotor(batch=args.batch)
