@@ -27,7 +27,10 @@ Notation follows the paper (Sec. 2 and Sec. 3):
 
 Inner products: states <a|b> = sum conj(a) b; gates <A|B> = Tr(A^dagger B)/d.
 
-Pins (tests/test_oracle_finite.py): closed-form spin rotations, unitarity,
+Crank-Nicolson map (Sec. 3): U_j = (I + L_j)^{-1}(I - L_j), L_j = (i tau/2) H_j, with the
+exact gradient 1/2 Im<chi_j|H_c|psi_j + psi_{j+1}>, (I - L_j) chi_j = lambda_{j+1}.
+
+Pins (tests/test_oracle_finite.py, tests/test_oracle_cn.py): closed-form spin rotations, unitarity,
 reversibility, overlap invariance, central finite differences of J_tau,
 scipy's Frechet derivative of expm, ISM == plain gradient iterates, Theorem 1
 (value and argmax by an independent linear solve), Theorem 2 per slice,
@@ -43,6 +46,8 @@ __all__ = [
     "forward", "backward", "inner", "objective", "gradient", "plain_gradient_method",
     "assemble", "boundaries", "intermediate_states", "ism_slice_gradient",
     "ism_gradient", "ism_iterate", "theorem1_functional", "theorem1_argmax",
+    "cn_generator", "step_unitary_cn", "step_unitaries_cn", "gradient_cn",
+    "plain_gradient_method_cn", "ism_gradient_cn", "ism_iterate_cn",
 ]
 
 
@@ -303,3 +308,111 @@ def theorem1_argmax(Ms, psi0, target, s, K):
             b[r:r + d] += beta[n] * Ms[n].conj().T @ target
     x = np.linalg.solve(A, b)
     return [np.array(psi0)] + [x[(n - 1) * d:n * d] for n in range(1, N)] + [np.array(target)]
+
+
+# ----------------------------------------------------------------------------
+# Crank-Nicolson step map (Sec. 3: the paper's own scheme for finite dimension)
+# ----------------------------------------------------------------------------
+
+def cn_generator(H: np.ndarray, tau: float) -> np.ndarray:
+    """L_j = (i tau / 2) H_j, so that the Crank-Nicolson step solves
+    (I + L_j) psi_{j+1} = (I - L_j) psi_j  (Sec. 3, time discretisation)."""
+    return 0.5j * tau * np.asarray(H, dtype=np.complex128)
+
+
+def step_unitary_cn(H: np.ndarray, tau: float) -> np.ndarray:
+    """U_j = (I + L_j)^{-1} (I - L_j): the Cayley transform of -i tau H_j, unitary for
+    Hermitian H_j."""
+    L = cn_generator(H, tau)
+    I = np.eye(L.shape[0], dtype=np.complex128)
+    return np.linalg.solve(I + L, I - L)
+
+
+def step_unitaries_cn(H0, Hc, u, tau):
+    return [step_unitary_cn(hamiltonian(H0, Hc, u[j]), tau) for j in range(u.shape[0])]
+
+
+def _cn_step_gradient(H, Hc, lam_next, psi_j, psi_next, tau):
+    """(1/tau) dJ/du_{j,c} of the Crank-Nicolson step, without the penalty (the discrete
+    gradient of Sec. 3 read as in the design notes):
+        chi_j solves (I - L_j) chi_j = lambda_{j+1},
+        g_{j,c} = 1/2 Im <chi_j | H_c | psi_j + psi_{j+1}>.
+    Derivation: U = (I+L)^{-1}(I-L) gives dU/du_c = -(i tau/2) (I+L)^{-1} H_c (I + U), and
+    ((I+L)^{-1})^dagger = (I-L)^{-1}."""
+    L = cn_generator(H, tau)
+    I = np.eye(L.shape[0], dtype=np.complex128)
+    chi = np.linalg.solve(I - L, lam_next)
+    s = psi_j + psi_next
+    return np.array([0.5 * inner(chi, Hc[c] @ s).imag for c in range(Hc.shape[0])])
+
+
+def gradient_cn(H0, Hc, psi0, target, u, T, alpha):
+    """Exact (1/tau) dJ_tau/du of the Crank-Nicolson step map, plus J and F at u.
+    Returns (g[K,C], J, F, psi_K)."""
+    K = u.shape[0]
+    tau = T / K
+    Us = step_unitaries_cn(H0, Hc, u, tau)
+    psis = forward(Us, psi0)
+    lams = backward(Us, target)
+    g = np.zeros_like(u)
+    for j in range(K):
+        H = hamiltonian(H0, Hc, u[j])
+        g[j] = _cn_step_gradient(H, Hc, lams[j + 1], psis[j], psis[j + 1], tau) - alpha[j] * u[j]
+    J, F = objective(psis[-1], target, u, alpha, tau)
+    return g, J, F, psis[-1]
+
+
+def plain_gradient_method_cn(H0, Hc, psi0, target, u0, T, alpha, rho, iters):
+    """Constant-step gradient ascent (Eq. (gradStep)) with the Crank-Nicolson map."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    tau = T / u.shape[0]
+    Js, Fs, Errs = [], [], []
+    for _ in range(iters):
+        g, J, F, _ = gradient_cn(H0, Hc, psi0, target, u, T, alpha)
+        Js.append(J); Fs.append(F); Errs.append(tau * float(np.sum(np.abs(g))))
+        u = u + rho * g
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs)}
+
+
+def ism_gradient_cn(H0, Hc, psi0, target, u, T, alpha, N):
+    """ISM gradient (Algorithm 1 steps (a)-(c)) with the Crank-Nicolson map: propagator
+    assembling, boundaries, intermediate states (Eq. (cible)); per slice the forward
+    trajectory from phi_n, the adjoint from phi_{n+1} and
+        beta_n [ 1/2 Im<chi^n_j|H_c|psi^n_j + psi^n_{j+1}> - alpha_{n,j} u_{j,c} ],
+    chi^n_j solving (I - L_j) chi^n_j = lambda^n_{j+1}.  Returns (g, J, F, phi, Psi, Lam)."""
+    K = u.shape[0]
+    tau = T / K
+    s = slice_starts(K, N)
+    Us = step_unitaries_cn(H0, Hc, u, tau)
+    Ms = assemble(Us, s)
+    Psi, Lam = boundaries(Ms, psi0, target)
+    phi = intermediate_states(Psi, Lam, s, K)
+    g = np.zeros_like(u)
+    for n in range(N):
+        sn, sn1 = s[n], s[n + 1]
+        beta = K / (sn1 - sn)
+        psi = [phi[n]]
+        for j in range(sn, sn1):
+            psi.append(Us[j] @ psi[-1])
+        lam = [None] * (sn1 - sn + 1)
+        lam[-1] = phi[n + 1]
+        for j in range(sn1 - 1, sn - 1, -1):
+            lam[j - sn] = Us[j].conj().T @ lam[j - sn + 1]
+        for j in range(sn, sn1):
+            H = hamiltonian(H0, Hc, u[j])
+            gj = _cn_step_gradient(H, Hc, lam[j - sn + 1], psi[j - sn], psi[j - sn + 1], tau)
+            g[j] = beta * (gj - (alpha[j] / beta) * u[j])
+    J, F = objective(Psi[-1], target, u, alpha, tau)
+    return g, J, F, phi, Psi, Lam
+
+
+def ism_iterate_cn(H0, Hc, psi0, target, u0, T, alpha, rho, iters, N):
+    """ISM with one gradient step per slice (Algorithm 1), Crank-Nicolson map."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    tau = T / u.shape[0]
+    Js, Fs, Errs = [], [], []
+    for _ in range(iters):
+        g, J, F, _, _, _ = ism_gradient_cn(H0, Hc, psi0, target, u, T, alpha, N)
+        Js.append(J); Fs.append(F); Errs.append(tau * float(np.sum(np.abs(g))))
+        u = u + rho * g
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs)}
