@@ -70,6 +70,17 @@ typedef enum ism_kind {
                                remark); <A|B> = Tr(A^dagger B)/d */
 } ism_kind;
 
+typedef enum ism_step_map {
+    ISM_STEP_EXP = 0,       /* psi_{j+1} = exp(-i tau H_j) psi_j, exact exponential */
+    ISM_STEP_CN = 1         /* Crank-Nicolson (Sec. 3): (I + L_j) psi_{j+1} = (I - L_j) psi_j,
+                               L_j = (i tau/2) H_j, with its exact gradient
+                               1/2 Im<chi_j|H_c|psi_j + psi_{j+1}>, (I - L_j) chi_j = lambda_{j+1}.
+                               State problems of the sparse path only; the inverse is applied as
+                               a Neumann series, so tau ||H_j||_inf / 2 must stay below 0.25
+                               (FP64) or 0.45 (FP32 mixed): steps beyond that make
+                               ism_gradient / ism_iterate return ISM_E_UNSUPPORTED. */
+} ism_step_map;
+
 typedef struct ism_options {
     int precision;          /* ism_precision (default ISM_FP64) */
     int kind;               /* ism_kind (default ISM_STATE) */
@@ -86,6 +97,7 @@ typedef struct ism_options {
                                stream-ordered on its stream (hipMallocAsync / hipFreeAsync), so
                                creating and destroying the handle never synchronises the whole
                                device (default 0: hipMalloc / hipFree) */
+    int step_map;           /* ism_step_map of a state problem (default ISM_STEP_EXP) */
 } ism_options;
 
 /* Fill *opt with the defaults listed above.  opt must not be NULL. */

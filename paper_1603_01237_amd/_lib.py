@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libism.so")
 ISM_OK, ISM_E_ARG, ISM_E_NOMEM, ISM_E_DEVICE, ISM_E_STATE, ISM_E_NUMERIC, ISM_E_UNSUPPORTED, ISM_E_BUDGET = range(8)
 FP64, FP32_MIXED = 0, 1
 STATE, GATE = 0, 1
+STEP_EXP, STEP_CN = 0, 1
+STEP_MAPS = {"exp": STEP_EXP, "cn": STEP_CN}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
 
 EXPORTED = [
@@ -41,7 +43,7 @@ class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("kind", ct.c_int), ("batch", ct.c_int),
                 ("h0_batched", ct.c_int), ("alpha", ct.POINTER(ct.c_double)),
                 ("alpha_len", ct.c_int), ("device", ct.c_int), ("stream", ct.c_void_p),
-                ("io_device", ct.c_int), ("alloc_async", ct.c_int)]
+                ("io_device", ct.c_int), ("alloc_async", ct.c_int), ("step_map", ct.c_int)]
 
 
 class Info(ct.Structure):
@@ -183,7 +185,8 @@ class Problem:
     # ------------------------------------------------------------------ creation
     @classmethod
     def create(cls, H0, Hc, psi0, target, T, K, N, precision="fp64", kind="state", batch=1,
-               h0_batched=False, alpha=None, device=0, stream=None, io_device=False):
+               h0_batched=False, alpha=None, device=0, stream=None, io_device=False,
+               step_map="exp"):
         L = lib()
         Hc = _as_c128(Hc)
         C, d = Hc.shape[0], Hc.shape[-1]
@@ -208,6 +211,7 @@ class Problem:
         o.device = int(device)
         o.stream = stream
         o.io_device = 1 if io_device else 0
+        o.step_map = STEP_MAPS[step_map] if isinstance(step_map, str) else int(step_map)
         h = ct.c_void_p()
         _check(L.ism_problem_create(ct.byref(h), d, C, _cptr(H0), _cptr(Hc), _cptr(psi0),
                                     _cptr(target), float(T), int(K), int(N), ct.byref(o)),
@@ -336,7 +340,7 @@ class Problem:
 
 
 def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=None,
-                 io_device=False, set_u=True):
+                 io_device=False, set_u=True, step_map="exp"):
     """Create a handle from a ``problems.FiniteProblem`` (or ``problems.GpeProblem``)."""
     if hasattr(prob, "V0"):
         B = prob.batch if batch is None else batch
@@ -353,7 +357,7 @@ def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=No
     p = Problem.create(H0, prob.Hc, prob.psi0, prob.target, prob.T, prob.K,
                        prob.N if N is None else N, precision=precision, kind=prob.kind, batch=B,
                        h0_batched=prob.H0.ndim == 3, alpha=al, device=device, stream=stream,
-                       io_device=io_device)
+                       io_device=io_device, step_map=step_map)
     if set_u:
         p.set_controls(prob.u0[:B])
     return p

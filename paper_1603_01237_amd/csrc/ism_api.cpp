@@ -129,6 +129,7 @@ int read_flags(ism_problem* p, int* host_flags) {
 int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism_options* o) {
     p->precision = o->precision;
     p->kind = o->kind;
+    p->step_cn = o->step_map == ISM_STEP_CN ? 1 : 0;
     p->B = o->batch;
     p->d = d;
     p->C = C;
@@ -173,6 +174,7 @@ int validate_common(int d, int C, double T, int K, int N, const ism_options* o) 
     if (!(T > 0.0) || !std::isfinite(T)) return ISM_E_ARG;
     if (o->batch < 1 || (o->precision != ISM_FP64 && o->precision != ISM_FP32_MIXED)) return ISM_E_ARG;
     if (o->kind != ISM_STATE && o->kind != ISM_GATE) return ISM_E_ARG;
+    if (o->step_map != ISM_STEP_EXP && o->step_map != ISM_STEP_CN) return ISM_E_ARG;
     if (o->alpha) {
         if (o->alpha_len != 1 && o->alpha_len != K) return ISM_E_ARG;
         if (!finite_all(o->alpha, o->alpha_len)) return ISM_E_ARG;
@@ -215,6 +217,7 @@ static SpArgs sp_args(ism_problem* p, int assemble) {
     a.update = 0;
     a.tau = p->tau;
     a.T = p->T;
+    a.cn = p->step_cn;
     return a;
 }
 
@@ -324,8 +327,9 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
     }
     const int vi = sp_variant_index(CG, WC, realh ? 1 : 0, d);
     if (vi < 0) return ISM_E_UNSUPPORTED;
+    if (p->step_cn && !sp_variant_cn(vi)) return ISM_E_UNSUPPORTED;
     // one real control operator with entries only at (r, r +- 1) and a diagonal H0
-    bool tri = CG == 1 && realh && !offdiag && WC <= 2 && sp_tri_supported(d);
+    bool tri = !p->step_cn && CG == 1 && realh && !offdiag && WC <= 2 && sp_tri_supported(d);
     for (int r = 0; tri && r < d; ++r)
         for (const auto& e : rows[0][r])
             if (e.first != r - 1 && e.first != r + 1) tri = false;
@@ -353,8 +357,13 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
     for (int b = 0; b < B; ++b) {
         const double* dg = diag.data() + (size_t)(h0_batched ? b : 0) * d;
         const double mx = *std::max_element(dg, dg + d), mn = *std::min_element(dg, dg + d);
-        shift[b] = 0.5 * (mx + mn);
-        h0norm[b] = 0.5 * (mx - mn);
+        if (p->step_cn) {              // the Cayley map takes no spectral shift
+            shift[b] = 0.0;
+            h0norm[b] = std::max(fabs(mx), fabs(mn));
+        } else {
+            shift[b] = 0.5 * (mx + mn);
+            h0norm[b] = 0.5 * (mx - mn);
+        }
     }
     int st;
     if ((st = dev_upload(p, (void**)&p->h0diag, diag.data(), diag.size() * sizeof(double)))) return st;
@@ -457,6 +466,7 @@ void ism_default_options(ism_options* o) {
     o->stream = nullptr;
     o->io_device = 0;
     o->alloc_async = 0;
+    o->step_map = ISM_STEP_EXP;
 }
 
 const char* ism_status_string(int s) {
@@ -520,7 +530,9 @@ int ism_problem_create(ism_problem** out, int d, int n_ctrl, const double* H0, c
     if (!p) return ISM_E_NOMEM;
     st = common_setup(p, d, n_ctrl, T, K, N, &o);
     if (!st) {
-        if (o.kind == ISM_GATE) {
+        if (o.kind == ISM_GATE && p->step_cn) {
+            st = ISM_E_UNSUPPORTED;
+        } else if (o.kind == ISM_GATE) {
             p->path = PATH_GATE;
             st = gate_create(p, H0, o.h0_batched, Hc, psi0, target);
         } else {
@@ -591,6 +603,7 @@ int ism_gradient(ism_problem* p, double* grad) {
     }
     int fl[4];
     if ((st = read_flags(p, fl))) return st;
+    if (fl[0] & 2) return ISM_E_UNSUPPORTED;
     if (fl[0]) return ISM_E_NUMERIC;
     return copy_out(p, grad, p->grad, n * sizeof(double));
 }
@@ -619,6 +632,7 @@ int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double*
         if (check_stop) {
             int fl[4];
             if ((st = read_flags(p, fl))) return st;
+            if (fl[0] & 2) return ISM_E_UNSUPPORTED;
             if (fl[0]) return ISM_E_NUMERIC;
             if (fl[1] == 0) break;
         }
@@ -627,6 +641,7 @@ int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double*
     }
     int fl[4];
     if ((st = read_flags(p, fl))) return st;
+    if (fl[0] & 2) return ISM_E_UNSUPPORTED;
     if (fl[0]) return ISM_E_NUMERIC;
     if (J_hist && n_iter > 0) {
         if ((st = copy_out(p, J_hist, p->Jhist, (size_t)n_iter * p->B * sizeof(double)))) return st;

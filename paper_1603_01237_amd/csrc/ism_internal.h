@@ -48,6 +48,7 @@ struct SpArgs {
     const int* active;     // B (nullable): 0 => instance frozen, no update
     double rho;
     int update;            // 1 => u += rho * g in place
+    int cn;                // 1 => Crank-Nicolson step map (tp.m = Neumann terms, S = 1)
     double tau, T;
 };
 
@@ -92,6 +93,7 @@ struct TimeScope {
 
 // kernel launchers (k_sparse.hip)
 int sp_variant_index(int CG, int WC, int realh, int d);
+bool sp_variant_cn(int variant);     // variant compiled with the Crank-Nicolson map
 hipError_t sp_launch_params(const SpArgs& a, const double* h0norm, const double* gnorm,
                             int precision, hipStream_t st, int* flags);
 hipError_t sp_launch_assemble(const SpArgs& a, int variant, int precision, hipStream_t st);
@@ -135,6 +137,7 @@ struct ism_problem {
     // sparse path
     int CG = 0, WC = 0, has_offdiag = 0, realh = 0, variant = -1;
     int tri = 0;               // generator is one real operator coupling rows r, r +- 1 only
+    int step_cn = 0;           // Crank-Nicolson step map instead of the exponential
     double* h0diag = nullptr;
     int h0diag_stride = 0;
     int* gcol = nullptr;

@@ -194,6 +194,7 @@ int advance(ism_server* s, Req* r) {
     int fl[4];
     memcpy(fl, slot + 2, sizeof(fl));
     r->inflight = false;
+    if (fl[0] & 2) return ISM_E_UNSUPPORTED;
     if (fl[0]) return ISM_E_NUMERIC;
     r->res.J = slot[0];
     r->res.F = slot[1];

@@ -701,6 +701,7 @@ extern "C" int ism_problem_create_gpe(ism_problem** out, int n_grid, double L, d
     ism_default_options(&o);
     if (opt) o = *opt;
     o.kind = ISM_STATE;
+    if (o.step_map != ISM_STEP_EXP) return ISM_E_UNSUPPORTED;   // the condensate uses Eq. (OS)
     if (n_grid != 1024 && n_grid != 4096) return n_grid > 0 ? ISM_E_UNSUPPORTED : ISM_E_ARG;
     if (!(L > 0.0) || !std::isfinite(L) || !std::isfinite(g) || !std::isfinite(V2)) return ISM_E_ARG;
     int st = validate_common(n_grid, 1, T, K, N, &o);

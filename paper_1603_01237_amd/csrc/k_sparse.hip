@@ -199,6 +199,57 @@ __device__ __forceinline__ void fwd_substep(R& xr, R& xi, Diag<R> d0,
     xi = pi;
 }
 
+// h = (D + sum_g Gs_g) p on this lane's row (generator pre-scaled, controls folded in)
+template <typename R, int CGM, int WCM, bool RH, class X>
+__device__ __forceinline__ void gen_h(R pr, R pi, Diag<R> d0, const Gen<R, CGM, WCM, RH>& Gs,
+                                      const X& ex, int r, R& hr, R& hi) {
+    ex.publish(0, r, pr);
+    ex.publish(1, r, pi);
+    ex.sync();
+    hr = d0.mul(pr);
+    hi = d0.mul(pi);
+#pragma unroll
+    for (int g = 0; g < CGM; ++g)
+#pragma unroll
+        for (int w = 0; w < WCM; ++w) {
+            const R nr = ex.fetch(0, Gs.addr[g][w], pr);
+            const R ni = ex.fetch(1, Gs.addr[g][w], pi);
+            if (RH) {
+                hr = fma(Gs.vre[g][w], nr, hr);
+                hi = fma(Gs.vre[g][w], ni, hi);
+            } else {
+                hr = fma(Gs.vre[g][w], nr, fma(-Gs.vim[g][w], ni, hr));
+                hi = fma(Gs.vre[g][w], ni, fma(Gs.vim[g][w], nr, hi));
+            }
+        }
+    ex.sync();
+}
+
+// The Crank-Nicolson map is compiled into the variants with at most four generators (the
+// larger ones are register-bound already); handles with more generators reject it.
+template <int CGM>
+constexpr bool kCnVariant = CGM <= 4;
+
+// Crank-Nicolson step (Sec. 3): x <- (I + L)^{-1} (I - L) x with L = i h, h = (tau/2) H (the
+// generator is pre-scaled by tau/2).  y = (I - L) x, then the Neumann series
+// z <- y - L z (nt times) for (I + L)^{-1} y, convergent since ||L|| < 1.
+template <typename R, int CGM, int WCM, bool RH, class X>
+__device__ __forceinline__ void fwd_cn(R& xr, R& xi, Diag<R> d0, const Gen<R, CGM, WCM, RH>& Gs,
+                                       const X& ex, int r, int nt) {
+    R hr, hi;
+    gen_h(xr, xi, d0, Gs, ex, r, hr, hi);
+    const R yr = xr + hi, yi = xi - hr;              // y = x - i h
+    R zr = yr, zi = yi;
+#pragma unroll 1
+    for (int k = 0; k < nt; ++k) {
+        gen_h(zr, zi, d0, Gs, ex, r, hr, hi);
+        zr = yr + hi;                                // z <- y - i h(z)
+        zi = yi - hr;
+    }
+    xr = zr;
+    xi = zi;
+}
+
 // One sub-step of the block exponential exp([[A^+, E^+],[0, A^+]]) with
 // A^+ = +i tau_sub (H - s), E_c^+ = +i tau_sub G_c, applied to (y_c, chi), and of
 // exp(A^+) applied to psi (reversal of the forward slice trajectory); Horner's rule on the
@@ -412,7 +463,10 @@ __global__ __launch_bounds__(256) void k_sp_assemble(SpArgs a) {
         fetch_controls<CGM>(a, im.b, jn, unext);
         const Gen<R, CGM, WCM, RH> Gs = scaled(G, v);
         R nr = xr, ni = xi;
-        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, Gs, ex, im.r, m);
+        if (kCnVariant<CGM> && a.cn)
+            fwd_cn(nr, ni, d0, Gs, ex, im.r, m);
+        else
+            for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, Gs, ex, im.r, m);
         if (act) {
             xr = nr;
             xi = ni;
@@ -462,7 +516,10 @@ __global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
         fetch_controls<CGM>(a, im.b, jn, unext);
         const Gen<R, CGM, WCM, RH> Gs = scaled(G, v);
         R nr = xr, ni = xi;
-        for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, Gs, ex, im.r, m);
+        if (kCnVariant<CGM> && a.cn)
+            fwd_cn(nr, ni, d0, Gs, ex, im.r, m);
+        else
+            for (int sub = 0; sub < S; ++sub) fwd_substep(nr, ni, d0, Gs, ex, im.r, m);
         if (act) {
             xr = nr;
             xi = ni;
@@ -494,6 +551,58 @@ __global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
         // the previous step's controls (not yet updated: step j-1 is updated in the next
         // pass of this loop) are requested before this step's series
         if (jl > 0) fetch_controls<CGM>(a, im.b, sn + (jl - 1 < L ? jl - 1 : L - 1), unext);
+        const double al = a.alpha ? a.alpha[j] : 0.0;
+        if constexpr (kCnVariant<CGM>) if (a.cn) {
+            // Crank-Nicolson adjoint step: with L = i h(.), chi~ = (I - L)^{-1} chi_{j+1} and
+            // psi~ = (I - L)^{-1} psi_{j+1} (Neumann series z <- b + L z), then
+            // chi_j = (I + L) chi~, psi_j = (I + L) psi~, and the gradient
+            // beta_n Im<chi~|H_c|psi~> (psi_j + psi_{j+1} = 2 psi~).
+            const Gen<R, CGM, WCM, RH> Gs = scaled(G, v);
+            R zcr = cr, zci = ci, zpr = pr, zpi = pi, hr, hi;
+#pragma unroll 1
+            for (int k = 0; k < m; ++k) {
+                gen_h(zcr, zci, d0, Gs, ex, im.r, hr, hi);
+                const R ncr = cr - hi, nci = ci + hr;    // b + i h(z)
+                gen_h(zpr, zpi, d0, Gs, ex, im.r, hr, hi);
+                zpr = pr - hi;
+                zpi = pi + hr;
+                zcr = ncr;
+                zci = nci;
+            }
+            // G_c psi~ (unscaled control operators, pre-scaled by tau/2) for the overlaps
+            ex.publish(0, im.r, zpr);
+            ex.publish(1, im.r, zpi);
+            ex.sync();
+            R gpr[CGM], gpi[CGM];
+            gen_apply(G, ex, 0, zpr, zpi, gpr, gpi);
+            ex.sync();
+            R hcr, hci, hpr, hpi;
+            gen_h(zcr, zci, d0, Gs, ex, im.r, hcr, hci);
+            gen_h(zpr, zpi, d0, Gs, ex, im.r, hpr, hpi);
+            if (act) {
+                cr = zcr - hci;                          // (I + L) z = z + i h(z)
+                ci = zci + hcr;
+                pr = zpr - hpi;
+                pi = zpi + hpr;
+            }
+            const double two_over_tau = 2.0 / a.tau;
+#pragma unroll
+            for (int c = 0; c < CGM; ++c) {
+                if (c >= a.C) break;
+                // Im <chi~ | G_c psi~> in FP64 (rows beyond d hold zeros)
+                const double xre = (double)zcr, xim = (double)zci;
+                const double yre = (double)gpr[c], yim = (double)gpi[c];
+                double oim = fma(xre, yim, -xim * yre);
+                oim = item_sum(oim, im.lane, im.r, a.d, ex);
+                if (act && im.r == 0) {
+                    const double g = ((double)a.K / (double)L) * two_over_tau * oim - al * ud[c];
+                    const size_t ui = ((size_t)im.b * a.K + j) * a.C + c;
+                    if (a.grad) a.grad[ui] = g;
+                    if (upd) a.u[ui] = fma(a.rho, g, ud[c]);
+                }
+            }
+            continue;
+        }
         R yr[CGM], yi[CGM];
 #pragma unroll
         for (int c = 0; c < CGM; ++c) yr[c] = yi[c] = 0;
@@ -506,7 +615,6 @@ __global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
             pr = npr;
             pi = npi;
         }
-        const double al = a.alpha ? a.alpha[j] : 0.0;
 #pragma unroll
         for (int c = 0; c < CGM; ++c) {
             if (c >= a.C) break;
@@ -557,6 +665,30 @@ __global__ __launch_bounds__(256) void k_sp_params(SpArgs a, const double* h0nor
         }
         bound += red[0] * gnorm[g];
         __syncthreads();
+    }
+    if (threadIdx.x == 0 && a.cn) {
+        // Crank-Nicolson: terms of the Neumann series of (I + L)^{-1}, ||L|| <= theta; steps
+        // outside the series' useful range are flagged (bit 2) and run one term
+        const double theta = 0.5 * a.tau * bound;
+        const double tol = PREC == 0 ? 1e-17 : 1e-10;
+        TaylorP tp;
+        tp.S = 1;
+        tp.m = 1;
+        tp.tau_sub = 0.5 * a.tau;
+        if (!(theta < 0.9)) {
+            atomicOr(&flags[0], theta == theta ? 2 : 1);
+        } else {
+            int nt = 1;
+            double t = theta * theta / (1.0 - theta);     // remainder after nt terms
+            while (nt < MMAX && t > tol) {
+                ++nt;
+                t *= theta;
+            }
+            if (t > tol) atomicOr(&flags[0], 2);
+            tp.m = nt;
+        }
+        const_cast<TaylorP*>(a.tp)[b] = tp;
+        return;
     }
     if (threadIdx.x == 0) {
         const double theta = a.tau * bound;
@@ -1157,6 +1289,8 @@ static size_t sp_block_shmem(int vi, int dp, int precision) {
 }
 
 }  // namespace
+
+bool sp_variant_cn(int vi) { return vi >= 0 && vi < kNumVariants && kVariants[vi].CG <= 4; }
 
 int sp_variant_index(int CG, int WC, int realh, int d) {
     if (d < 1 || d > 256) return -1;

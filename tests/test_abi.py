@@ -45,6 +45,7 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw", [
+    {"step_map": 7},           # no such step map
     {"N": 11},                 # N > K
     {"N": 0},
     {"K": 0, "N": 0},
