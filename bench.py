@@ -153,11 +153,15 @@ def gpe_sweep_flops(prob):
     return 2.0 * prob.K * 2 * 5 * prob.n * math.log2(prob.n) * prob.batch
 
 
-def other_workloads(stream, iters_gate=2, iters_gpe=2, which=("spins", "gate", "gpe")):
+def other_workloads(stream, iters_gate=2, iters_gpe=2,
+                    which=("spins", "gate", "gpe", "rotor_cn")):
     """The paper's other benchmark shapes: the two-spin solve (latency), gate synthesis
-    on MFMA and the condensate (sequential FFT sweeps)."""
+    on MFMA, the condensate (sequential FFT sweeps), and the rotor batch with the
+    Crank-Nicolson step map."""
     import problems
     out = {}
+    if "rotor_cn" in which:
+        out.update(_rotor_cn_workload(stream))
     if "spins" in which:
         out.update(_spins_workload(stream))
     if "gate" in which:
@@ -165,6 +169,32 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2, which=("spins", "gate", "
     if "gpe" in which:
         out.update(_gpe_workload(stream, iters_gpe))
     return out
+
+
+def _rotor_cn_workload(stream, steps=3):
+    """The benchmark's rotor batch with the Crank-Nicolson map (Sec. 3): each step is
+    (I - L) then the Neumann series of (I + L)^{-1}, n terms from the norm bound."""
+    import problems
+    prob = problems.rotor()
+    B = prob.batch
+    r = {prec: run_gpu(prec, prob, steps, 1, stream, step_map="cn") for prec in ("fp32", "fp64")}
+    ent = {"workload": f"rotor batch with the Crank-Nicolson map: {B} instances, d=21, "
+                       f"K={prob.K}, N={prob.N}",
+           "ms_per_iteration": {k: v["seconds"] / steps * 1e3 for k, v in r.items()},
+           "useful_steps_per_s": {k: B * 2 * prob.K * steps / v["seconds"] for k, v in r.items()},
+           "neumann_terms": {k: v["info"]["taylor_m"] for k, v in r.items()},
+           "kernels_ms_per_iteration": {k: {n: t[1] / steps for n, t in v["kernels"].items()}
+                                        for k, v in r.items()},
+           "final_F_mean": {k: v["F_mean"] for k, v in r.items()}}
+    for prec, v in r.items():
+        launches, ms = v["kernels"]["sp_assemble"]
+        # (n + 1) applications of tau/2 H per step: (I - L) and n Neumann terms
+        fl = algorithmic_flops(prob, v["info"]["taylor_m"] + 1, 1, B)["sp_assemble"]
+        ach = fl / (ms / launches * 1e-3)
+        ent[f"roofline_{prec}"] = {"bound": "alu", "kernel": "sp_assemble", "achieved": ach / 1e12,
+                                   "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
+                                   "frac": ach / PEAK_ALU}
+    return {"rotor_cn": ent}
 
 
 def _spins_workload(stream):
@@ -224,12 +254,12 @@ def _gpe_workload(stream, iters_gpe):
     return out
 
 
-def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True):
+def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp"):
     """Warm-up iterations, controls reset to u0, then `steps` timed iterations (per-kernel
     HIP events on the handle's stream when `timing`)."""
     import torch
     from paper_1603_01237_amd import _lib
-    h = _lib.from_problem(prob, precision=prec, stream=stream_ptr)
+    h = _lib.from_problem(prob, precision=prec, stream=stream_ptr, step_map=step_map)
     h.iterate(warmup, prob.rho, record=False)
     h.set_controls(prob.u0)
     torch.cuda.synchronize()
@@ -278,7 +308,7 @@ def main():
                     help="skip the two-spin, gate and condensate workloads")
     ap.add_argument("--serve", type=int, default=16,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
-    ap.add_argument("--only", choices=["spins", "gate", "gpe"],
+    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn"],
                     help="run only this secondary workload and print its figures (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the streaming kernel that scales the HBM byte counters")

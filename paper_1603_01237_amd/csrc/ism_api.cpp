@@ -329,7 +329,7 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
     if (vi < 0) return ISM_E_UNSUPPORTED;
     if (p->step_cn && !sp_variant_cn(vi)) return ISM_E_UNSUPPORTED;
     // one real control operator with entries only at (r, r +- 1) and a diagonal H0
-    bool tri = !p->step_cn && CG == 1 && realh && !offdiag && WC <= 2 && sp_tri_supported(d);
+    bool tri = CG == 1 && realh && !offdiag && WC <= 2 && sp_tri_supported(d);
     for (int r = 0; tri && r < d; ++r)
         for (const auto& e : rows[0][r])
             if (e.first != r - 1 && e.first != r + 1) tri = false;

@@ -992,6 +992,110 @@ __device__ __forceinline__ void tri_fwd_substep(R (&nr)[RPL], R (&ni)[RPL], cons
     }
 }
 
+// Crank-Nicolson step in the tridiagonal layout: x <- (I + L)^{-1} (I - L) x, L = i h, by
+// y = (I - L) x and the Neumann series z <- y - L z (nt terms); in FP32 the rounding residual
+// of the diagonal enters as e^{-2 i delta} (the Cayley map's first-order response to a
+// diagonal shift), applied once per step.
+template <typename R>
+__device__ __forceinline__ void tri_fwd_cn(R (&nr)[RPL], R (&ni)[RPL], const R (&dg)[RPL],
+                                           const R (&dl)[RPL], const R (&Ls)[RPL],
+                                           const R (&Rs)[RPL], int left, int right, int nt) {
+    R lr, li, rr, ri, hr[RPL], hi[RPL], yr[RPL], yi[RPL];
+    tri_edges(nr, ni, left, right, lr, li, rr, ri);
+    tri_apply(nr, ni, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        yr[q] = nr[q] + hi[q];                            // y = x - i h
+        yi[q] = ni[q] - hr[q];
+        nr[q] = yr[q];
+        ni[q] = yi[q];
+    }
+#pragma unroll 1
+    for (int k = 0; k < nt; ++k) {
+        tri_edges(nr, ni, left, right, lr, li, rr, ri);
+        tri_apply(nr, ni, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            nr[q] = yr[q] + hi[q];                        // z <- y - i h(z)
+            ni[q] = yi[q] - hr[q];
+        }
+    }
+    if (sizeof(R) == 4) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const R t = nr[q], d2 = 2 * dl[q];
+            nr[q] = fma(d2, ni[q], nr[q]);
+            ni[q] = fma(-d2, t, ni[q]);
+        }
+    }
+}
+
+// Crank-Nicolson adjoint step in the tridiagonal layout: with L = i h, chi~ = (I - L)^{-1} chi
+// and psi~ = (I - L)^{-1} psi (Neumann series z <- b + L z), then chi <- (I + L) chi~,
+// psi <- (I + L) psi~ (and e^{+2 i delta} in FP32).  Leaves chi~ in (zcr, zci) and the
+// unscaled control operator applied to psi~ in (gr, gi).
+template <typename R>
+__device__ __forceinline__ void tri_adj_cn(R (&cr)[RPL], R (&ci)[RPL], R (&pr)[RPL], R (&pi)[RPL],
+                                           R (&zcr)[RPL], R (&zci)[RPL], R (&gr)[RPL],
+                                           R (&gi)[RPL], const R (&dg)[RPL], const R (&dl)[RPL],
+                                           const R (&Lc)[RPL], const R (&Rc)[RPL],
+                                           const R (&Ls)[RPL], const R (&Rs)[RPL], int left,
+                                           int right, int nt) {
+    R zpr[RPL], zpi[RPL], lr, li, rr, ri, hr[RPL], hi[RPL];
+    const R zero[RPL] = {};
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        zcr[q] = cr[q];
+        zci[q] = ci[q];
+        zpr[q] = pr[q];
+        zpi[q] = pi[q];
+    }
+#pragma unroll 1
+    for (int k = 0; k < nt; ++k) {
+        tri_edges(zcr, zci, left, right, lr, li, rr, ri);
+        tri_apply(zcr, zci, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+        R ncr[RPL], nci[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            ncr[q] = cr[q] - hi[q];                       // b + i h(z)
+            nci[q] = ci[q] + hr[q];
+        }
+        tri_edges(zpr, zpi, left, right, lr, li, rr, ri);
+        tri_apply(zpr, zpi, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            zpr[q] = pr[q] - hi[q];
+            zpi[q] = pi[q] + hr[q];
+            zcr[q] = ncr[q];
+            zci[q] = nci[q];
+        }
+    }
+    tri_edges(zpr, zpi, left, right, lr, li, rr, ri);
+    tri_apply(zpr, zpi, lr, li, rr, ri, zero, Lc, Rc, gr, gi);      // G psi~
+    tri_apply(zpr, zpi, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        pr[q] = zpr[q] - hi[q];                           // (I + L) psi~
+        pi[q] = zpi[q] + hr[q];
+    }
+    tri_edges(zcr, zci, left, right, lr, li, rr, ri);
+    tri_apply(zcr, zci, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        cr[q] = zcr[q] - hi[q];                           // (I + L) chi~
+        ci[q] = zci[q] + hr[q];
+        if (sizeof(R) == 4) {
+            const R d2 = 2 * dl[q];
+            R t = cr[q];
+            cr[q] = fma(-d2, ci[q], cr[q]);
+            ci[q] = fma(d2, t, ci[q]);
+            t = pr[q];
+            pr[q] = fma(-d2, pi[q], pr[q]);
+            pi[q] = fma(d2, t, pi[q]);
+        }
+    }
+}
+
 // One sub-step of the block exponential of adj_substep in the tridiagonal layout:
 // (y, chi) <- exp([[A^+, E^+], [0, A^+]]) (y, chi) and psi <- exp(A^+) psi, with
 // A^+ = +i (D + v G), E^+ = +i G (G the unscaled control operator), then e^{+i delta} on
@@ -1111,7 +1215,10 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
             nr[q] = xr[q];
             ni[q] = xi[q];
         }
-        for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
+        if (a.cn)
+            tri_fwd_cn(nr, ni, dg, dl, Ls, Rs, left, right, m);
+        else
+            for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
         if (act) {
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
@@ -1184,7 +1291,10 @@ __global__ __launch_bounds__(256) void k_sp_slice_tri(SpArgs a) {
             nr[q] = xr[q];
             ni[q] = xi[q];
         }
-        for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
+        if (a.cn)
+            tri_fwd_cn(nr, ni, dg, dl, Ls, Rs, left, right, m);
+        else
+            for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
         if (act) {
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
@@ -1227,6 +1337,34 @@ __global__ __launch_bounds__(256) void k_sp_slice_tri(SpArgs a) {
             npr[q] = xr[q];
             npi[q] = xi[q];
             yr[q] = yi[q] = 0;
+        }
+        if (a.cn) {
+            // chi~ in (yr, yi) and G psi~ in (zgr, zgi): the gradient is
+            // beta_n (2/tau) Im<chi~|G psi~> (G pre-scaled by tau/2)
+            R zgr[RPL], zgi[RPL];
+            tri_adj_cn(ncr, nci, npr, npi, yr, yi, zgr, zgi, dg, dl, Lc, Rc, Ls, Rs, left, right, m);
+            double oim = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+                oim += fma((double)yr[q], (double)zgi[q], -(double)yi[q] * (double)zgr[q]);
+            oim = lanes_sum(oim, lane, li, LPI);
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    cr[q] = ncr[q];
+                    ci[q] = nci[q];
+                    xr[q] = npr[q];
+                    xi[q] = npi[q];
+                }
+            }
+            if (act && li == 0) {
+                const double al = a.alpha ? a.alpha[j] : 0.0;
+                const double g = ((double)a.K / (double)L) * (2.0 / a.tau) * oim - al * ud;
+                const size_t ui = (size_t)b * a.K + j;
+                if (a.grad) a.grad[ui] = g;
+                if (upd) a.u[ui] = fma(a.rho, g, ud);
+            }
+            continue;
         }
         for (int sub = 0; sub < S; ++sub)
             tri_adj_substep(ncr, nci, npr, npi, yr, yi, dg, dl, Lc, Rc, Ls, Rs, v, left, right, m);

@@ -91,3 +91,26 @@ def test_cn_unsupported_paths():
     with pytest.raises(_lib.IsmError) as e:
         _lib.from_problem(chain, step_map="cn")
     assert e.value.code == _lib.ISM_E_UNSUPPORTED
+
+
+def test_cn_rotor_full_size_sampled():
+    """The benchmark's rotor batch (256 rotors, K=20000, N=128) with the Crank-Nicolson map,
+    FP32 mixed and FP64; two instances checked against the oracle.  FP64 bar as for the
+    exponential map at this K (random-walk rounding, 2e-14 sqrt(K))."""
+    from paper_1603_01237_amd import _lib
+    _say("case cn rotor full size")
+    p = problems.rotor()
+    tol64 = max(1e-12, 2e-14 * np.sqrt(p.K))
+    res = {}
+    for prec in ("fp32", "fp64"):
+        with _lib.from_problem(p, precision=prec, step_map="cn") as h:
+            res[prec] = (h.gradient(), h.forward())
+    for b in (0, 255):
+        gr, Jr, Fr, psiK = O.gradient_cn(p.H0[b], p.Hc, p.psi0, p.target, p.u0[b], p.T, p.alpha)
+        g64, psi64 = res["fp64"][0][b], res["fp64"][1][b]
+        g32, psi32 = res["fp32"][0][b], res["fp32"][1][b]
+        _say("instance", b, "fp64 g", _rel(g64, gr), "psi", _rel(psi64, psiK),
+             "fp32 g", _rel(g32, gr), "psi", np.linalg.norm(psi32 - psiK))
+        assert _rel(psi64, psiK) <= tol64 and _rel(g64, gr) <= tol64
+        assert np.linalg.norm(psi32 - psiK) <= 1e-4
+        assert _rel(g32, gr) <= 1e-3
