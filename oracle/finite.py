@@ -30,12 +30,21 @@ Inner products: states <a|b> = sum conj(a) b; gates <A|B> = Tr(A^dagger B)/d.
 Crank-Nicolson map (Sec. 3): U_j = (I + L_j)^{-1}(I - L_j), L_j = (i tau/2) H_j, with the
 exact gradient 1/2 Im<chi_j|H_c|psi_j + psi_{j+1}>, (I - L_j) chi_j = lambda_{j+1}.
 
-Pins (tests/test_oracle_finite.py, tests/test_oracle_cn.py): closed-form spin rotations, unitarity,
+Several gradient steps per slice (Algorithm 1 step (c) with Eq. (gradStep) iterated ell
+times on the slice problem max J_n[., phi^(k)], the intermediate states held fixed):
+    u_n <- u_n + rho beta_n grad J_n[u_n, phi^(k)]          (ell times)
+(the step is scaled by beta_n so that ell = 1 is the plain gradient step, Theorem 2), then
+Algorithm 1 step (e): Err = sum_n tau sum_{j in slice n} || grad J_n[u^(k+1), phi^(k)]_j ||_2,
+the Euclidean norm taken over the controls of step j; the loop runs while Err > eta.
+
+Pins (tests/test_oracle_finite.py, tests/test_oracle_cn.py, tests/test_oracle_inner.py): closed-form spin rotations, unitarity,
 reversibility, overlap invariance, central finite differences of J_tau,
 scipy's Frechet derivative of expm, ISM == plain gradient iterates, Theorem 1
 (value and argmax by an independent linear solve), Theorem 2 per slice,
 assembled boundaries == sequential propagation, rotor Gauss-Legendre nodes,
-free-rotor phases.  No function here is parity-unpinned.
+free-rotor phases, slice-problem gradients and Err against central finite differences of
+J_n, ell = 1 == plain method, N = 1 with ell steps == plain method with ell steps per
+iteration.  No function here is parity-unpinned.
 """
 from __future__ import annotations
 
@@ -48,6 +57,7 @@ __all__ = [
     "ism_gradient", "ism_iterate", "theorem1_functional", "theorem1_argmax",
     "cn_generator", "step_unitary_cn", "step_unitaries_cn", "gradient_cn",
     "plain_gradient_method_cn", "ism_gradient_cn", "ism_iterate_cn",
+    "subproblem_objective", "subproblem_gradient", "ism_iterate_inner",
 ]
 
 
@@ -416,3 +426,102 @@ def ism_iterate_cn(H0, Hc, psi0, target, u0, T, alpha, rho, iters, N):
         Js.append(J); Fs.append(F); Errs.append(tau * float(np.sum(np.abs(g))))
         u = u + rho * g
     return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs)}
+
+
+# ----------------------------------------------------------------------------
+# Several gradient steps per slice problem and the Err stopping rule (Algorithm 1)
+# ----------------------------------------------------------------------------
+
+def _slice_maps(H0, Hc, u, sn, sn1, tau, step):
+    """Step maps of the steps sn..sn1-1 under the controls u (full (K, C) array), as a
+    length-K list with the entries outside the slice left empty."""
+    K = u.shape[0]
+    Us = [None] * K
+    if step == "cn":
+        Us[sn:sn1] = step_unitaries_cn(H0, Hc, u[sn:sn1], tau)
+    else:
+        Us[sn:sn1] = step_unitaries(H0, Hc, u[sn:sn1], tau)
+    return Us
+
+
+def subproblem_objective(H0, Hc, u, alpha, phi_n, phi_n1, sn, sn1, T, step="exp"):
+    """Slice functional in its Re-form (Sec. 2):
+        J_n = Re<psi_n(t_{n+1})|phi_{n+1}> - alpha_n/2 tau sum_{j in slice} |u_j|^2,
+    psi_n propagated from phi_n over steps sn..sn1-1 (Eq. (dirpara)), alpha_n = alpha/beta_n."""
+    K = u.shape[0]
+    tau = T / K
+    beta = K / (sn1 - sn)
+    Us = _slice_maps(H0, Hc, u, sn, sn1, tau, step)
+    psi = phi_n
+    for j in range(sn, sn1):
+        psi = Us[j] @ psi
+    pen = 0.5 * tau * float(np.sum((alpha[sn:sn1] / beta)[:, None] * u[sn:sn1] ** 2))
+    return inner(psi, phi_n1).real - pen
+
+
+def subproblem_gradient(H0, Hc, u, alpha, phi_n, phi_n1, sn, sn1, T, step="exp"):
+    """beta_n grad J_n[u, phi] on the steps sn..sn1-1, with grad J_n = (1/tau) dJ_n/du_j
+    (the exact discrete gradient of the slice functional for the chosen step map).
+    Returns an (sn1 - sn, C) array."""
+    K = u.shape[0]
+    tau = T / K
+    if step != "cn":
+        Us = _slice_maps(H0, Hc, u, sn, sn1, tau, step)
+        Hhats = [None] * K
+        for j in range(sn, sn1):
+            Hhats[j] = hhat(hamiltonian(H0, Hc, u[j]), Hc, tau)
+        g, _ = ism_slice_gradient(Us, Hhats, u, alpha, phi_n, phi_n1, sn, sn1, K)
+        return g
+    beta = K / (sn1 - sn)
+    Us = _slice_maps(H0, Hc, u, sn, sn1, tau, "cn")
+    psi = [phi_n]
+    for j in range(sn, sn1):
+        psi.append(Us[j] @ psi[-1])
+    lam = [None] * (sn1 - sn + 1)
+    lam[-1] = phi_n1
+    for j in range(sn1 - 1, sn - 1, -1):
+        lam[j - sn] = Us[j].conj().T @ lam[j - sn + 1]
+    g = np.zeros((sn1 - sn, u.shape[1]))
+    for j in range(sn, sn1):
+        H = hamiltonian(H0, Hc, u[j])
+        gj = _cn_step_gradient(H, Hc, lam[j - sn + 1], psi[j - sn], psi[j - sn + 1], tau)
+        g[j - sn] = beta * (gj - (alpha[j] / beta) * u[j])
+    return g
+
+
+def ism_iterate_inner(H0, Hc, psi0, target, u0, T, alpha, rho, iters, N, ell, eta=0.0,
+                      step="exp"):
+    """Algorithm 1 with step (c) = ell constant-step gradient steps on every slice problem.
+
+    Iteration k: boundaries and intermediate states phi^(k) at u^(k) (steps (a)-(b), by
+    propagator assembling); on each slice, ell steps u_n <- u_n + rho beta_n grad J_n[u_n,
+    phi^(k)] (steps (c)-(d)); then Err^(k) = sum_n tau sum_j ||grad J_n[u^(k+1), phi^(k)]_j||
+    (step (e)).  The loop stops after the iteration whose Err is <= eta (eta <= 0: never).
+    Returns {"u", "J", "F", "Err", "iters"}: J^(k), F^(k) at u^(k) and Err^(k) for every
+    iteration run, "iters" the number of iterations run."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    K = u.shape[0]
+    tau = T / K
+    s = slice_starts(K, N)
+    maps = step_unitaries_cn if step == "cn" else step_unitaries
+    Js, Fs, Errs = [], [], []
+    for _ in range(iters):
+        Ms = assemble(maps(H0, Hc, u, tau), s)
+        Psi, Lam = boundaries(Ms, psi0, target)
+        phi = intermediate_states(Psi, Lam, s, K)
+        J, F = objective(Psi[-1], target, u, alpha, tau)
+        Js.append(J); Fs.append(F)
+        err = 0.0
+        for n in range(N):
+            sn, sn1 = s[n], s[n + 1]
+            beta = K / (sn1 - sn)
+            for _l in range(ell):
+                g = subproblem_gradient(H0, Hc, u, alpha, phi[n], phi[n + 1], sn, sn1, T, step)
+                u[sn:sn1] = u[sn:sn1] + rho * g
+            g = subproblem_gradient(H0, Hc, u, alpha, phi[n], phi[n + 1], sn, sn1, T, step)
+            err += tau * float(np.sum(np.sqrt(np.sum((g / beta) ** 2, axis=1))))
+        Errs.append(err)
+        if eta > 0 and err <= eta:
+            break
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs),
+            "iters": len(Errs)}

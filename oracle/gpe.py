@@ -29,17 +29,23 @@ sequential forward and one sequential adjoint sweep (propagator assembling is
 not defined for a nonlinear map), so each slice gradient equals the plain
 gradient on that slice by the chain rule (weight 1, no beta_n).
 
-Pins (tests/test_oracle_gpe.py): g=0 ground state is the harmonic-oscillator
+Several gradient steps per slice (Algorithm 1 step (c), Eq. (gradStep) iterated ell times on
+max J_n with psi(t_n) and nu(t_{n+1}) held fixed): u_n <- u_n + rho grad J_n, ell times;
+Err = sum_n tau sum_{j in slice n} |grad J_n[u^(k+1)]_j| (Algorithm 1 step (e)).
+
+Pins (tests/test_oracle_gpe.py, tests/test_oracle_inner.py): g=0 ground state is the harmonic-oscillator
 Gaussian, norm conservation, Ehrenfest leapfrog identities per step, adjoint
-gradient vs central finite differences, ISM == plain.  No function here is
-parity-unpinned.
+gradient vs central finite differences, ISM == plain, slice-problem gradient and Err vs
+central finite differences of J_n, ell = 1 == plain, N = 1 with ell steps == plain.  No
+function here is parity-unpinned.
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = ["grid", "potential", "dpotential", "strang_forward", "adjoint_gradient",
-           "objective", "plain_gradient_method", "ism_bec_gradient", "ism_bec_iterate"]
+           "objective", "plain_gradient_method", "ism_bec_gradient", "ism_bec_iterate",
+           "bec_subproblem_objective", "bec_subproblem_gradient", "ism_bec_iterate_inner"]
 
 
 def grid(n, L):
@@ -163,3 +169,51 @@ def ism_bec_iterate(psi0, target, u0, V0, V1, V2, gnl, L, T, rho, iters, N):
         Js.append(J); Fs.append(F)
         u = u + rho * g
     return {"u": u, "J": np.array(Js), "F": np.array(Fs)}
+
+
+def bec_subproblem_objective(psi_n, nu_n1, u_slice, V0, V1, V2, gnl, L, tau):
+    """BEC slice functional (Sec. 4.C): J_n = Re<psi_n(t_{n+1})|nu(t_{n+1})>, psi_n propagated
+    from psi(t_n) = psi_n under the slice controls u_slice."""
+    dx = L / psi_n.shape[0]
+    end, _ = strang_forward(psi_n, u_slice, V0, V1, V2, gnl, L, tau, keep=False)
+    return float((dx * np.vdot(end, nu_n1)).real)
+
+
+def bec_subproblem_gradient(psi_n, nu_n1, u_slice, V0, V1, V2, gnl, L, tau):
+    """(1/tau) dJ_n/du_j on the slice: forward from psi(t_n), exact adjoint from nu(t_{n+1})."""
+    dx = L / psi_n.shape[0]
+    _, rec = strang_forward(psi_n, u_slice, V0, V1, V2, gnl, L, tau)
+    _, g = _adjoint_steps(np.array(nu_n1, dtype=np.complex128), rec, u_slice, V1, V2, gnl, L,
+                          tau, 0, u_slice.shape[0], dx)
+    return g
+
+
+def ism_bec_iterate_inner(psi0, target, u0, V0, V1, V2, gnl, L, T, rho, iters, N, ell,
+                          eta=0.0):
+    """BEC-variant ISM with ell gradient steps per slice problem and the Err rule.
+
+    Iteration k: sequential sweeps give psi(t_n) and nu(t_n) at u^(k); each slice takes ell
+    steps u_n <- u_n + rho grad J_n; Err^(k) = sum_n tau sum_j |grad J_n[u^(k+1)]_j|.  The
+    loop stops after the iteration whose Err is <= eta (eta <= 0: never).  Returns
+    {"u", "J", "F", "Err", "iters"} as the finite-dimensional version."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    K = u.shape[0]
+    tau = T / K
+    Js, Fs, Errs = [], [], []
+    for _ in range(iters):
+        _, J, F, psi_b, nu_b = ism_bec_gradient(psi0, target, u, V0, V1, V2, gnl, L, T, N)
+        Js.append(J); Fs.append(F)
+        s = [(i * K) // N for i in range(N + 1)]
+        err = 0.0
+        for i in range(N):
+            a, b = s[i], s[i + 1]
+            for _l in range(ell):
+                g = bec_subproblem_gradient(psi_b[i], nu_b[i + 1], u[a:b], V0, V1, V2, gnl, L, tau)
+                u[a:b] = u[a:b] + rho * g
+            g = bec_subproblem_gradient(psi_b[i], nu_b[i + 1], u[a:b], V0, V1, V2, gnl, L, tau)
+            err += tau * float(np.sum(np.abs(g)))
+        Errs.append(err)
+        if eta > 0 and err <= eta:
+            break
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs), "Err": np.array(Errs),
+            "iters": len(Errs)}

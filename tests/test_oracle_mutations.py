@@ -151,3 +151,19 @@ def test_gpe_mutation_kinetic_sign(monkeypatch):
         return nu, g
     monkeypatch.setattr(G, "_adjoint_steps", bad_adjoint)
     assert _gpe_fd_error() > 1e-6
+
+
+def test_mutation_inner_step_without_beta(monkeypatch):
+    """An inner step that forgets the beta_n scale is no longer the plain step for ell = 1."""
+    H0, Hc, psi0, tgt, u, T, al = _tiny()
+    kw = dict(H0=H0, Hc=Hc, psi0=psi0, target=tgt, u0=u, T=T, alpha=al, rho=0.3, iters=3)
+    plain = O.plain_gradient_method(**kw)
+    ok = O.ism_iterate_inner(N=4, ell=1, **kw)
+    assert np.max(np.abs(ok["u"] - plain["u"])) <= 1e-10
+    orig = O.subproblem_gradient
+
+    def unscaled(H0_, Hc_, v, al_, phi_n, phi_n1, sn, sn1, T_, step="exp"):
+        return orig(H0_, Hc_, v, al_, phi_n, phi_n1, sn, sn1, T_, step) * (sn1 - sn) / v.shape[0]
+    monkeypatch.setattr(O, "subproblem_gradient", unscaled)
+    bad = O.ism_iterate_inner(N=4, ell=1, **kw)
+    assert np.max(np.abs(bad["u"] - plain["u"])) > 1e-3
