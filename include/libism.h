@@ -180,6 +180,29 @@ int ism_gradient(ism_problem* p, double* grad);
 int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double* J_hist,
                 int* iters_done);
 
+/*
+ * ISM iterations with several gradient steps per slice problem and the Err stopping rule
+ * (Algorithm 1, steps (c) and (e); Eq. (gradStep) iterated).  Iteration k rebuilds the
+ * boundaries and intermediate states phi^(k) at u^(k) (steps (a)-(b)), then every slice n
+ * takes n_inner constant steps on its own problem max J_n[., phi^(k)] with phi^(k) held:
+ *     u_n <- u_n + rho beta_n grad J_n[u_n, phi^(k)]                      (n_inner times)
+ * (scaled by beta_n so that n_inner = 1 is exactly ism_iterate), and finally
+ *     Err^(k) = sum_n tau sum_{j in slice n} || grad J_n[u^(k+1), phi^(k)]_j ||_2
+ * (Euclidean norm over the controls of step j).  Gross-Pitaevskii problems use the slice
+ * problems of the BEC variant (Sec. 4.C), whose gradients carry no beta_n.
+ *   n_inner   >= 1 (else ISM_E_ARG).
+ *   err_stop  eta > 0: an instance whose Err^(k) <= eta is frozen after iteration k, and
+ *             the loop ends once every instance is frozen; <= 0: no Err rule.
+ *   fid_stop, J_hist, iters_done: as ism_iterate.
+ *   Err_hist  nullable; receives Err^(k) in Err_hist[k*B + b] for the *iters_done
+ *             iterations run (entries past that are not written).  Err costs one more
+ *             slice pass per iteration and is only computed when err_stop > 0 or
+ *             Err_hist is non-NULL.
+ * ISM_E_NUMERIC if J or Err becomes NaN/Inf; ISM_E_UNSUPPORTED as ism_iterate.
+ */
+int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, double fid_stop,
+                      double err_stop, double* J_hist, double* Err_hist, int* iters_done);
+
 /* J = Re<psi(T)|psi_f> - tau/2 sum_j alpha_j |u_j|^2 and F = |<psi(T)|psi_f>|^2 per instance
  * (gate: Re Tr(W^+ U)/d and |Tr(W^+ U)|^2/d^2), B doubles each (either may be NULL).
  * Recomputes the boundaries if the controls changed since the last forward pass. */

@@ -24,7 +24,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
 EXPORTED = [
     "ism_default_options", "ism_problem_create", "ism_problem_create_gpe", "ism_problem_destroy",
     "ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient",
-    "ism_iterate", "ism_fidelity", "ism_problem_info", "ism_status_string", "ism_problem_footprint",
+    "ism_iterate", "ism_iterate_inner", "ism_fidelity", "ism_problem_info", "ism_status_string", "ism_problem_footprint",
     "ism_set_timing", "ism_kernel_times",
     "ism_server_clock", "ism_server_create", "ism_server_submit", "ism_server_progress",
     "ism_server_poll", "ism_server_take", "ism_server_stats_get", "ism_server_destroy",
@@ -112,6 +112,8 @@ def lib():
                  "ism_gradient"):
         getattr(L, name).argtypes = [vp, vp]
     L.ism_iterate.argtypes = [vp, ct.c_int, ct.c_double, ct.c_double, vp, ct.POINTER(ct.c_int)]
+    L.ism_iterate_inner.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_double,
+                                    vp, vp, ct.POINTER(ct.c_int)]
     L.ism_fidelity.argtypes = [vp, vp, vp]
     L.ism_problem_info.argtypes = [vp, ct.POINTER(Info)]
     L.ism_status_string.argtypes = [ct.c_int]
@@ -138,7 +140,7 @@ def lib():
         getattr(L, name).restype = ct.c_int
     for name in ("ism_problem_create", "ism_problem_create_gpe", "ism_set_controls",
                  "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient", "ism_iterate",
-                 "ism_fidelity", "ism_problem_info"):
+                 "ism_iterate_inner", "ism_fidelity", "ism_problem_info"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -316,6 +318,22 @@ class Problem:
         if Jh is not None:
             Jh = Jh[:n_iter]
         return Jh, done.value
+
+    def iterate_inner(self, n_iter, n_inner, rho, fid_stop=2.0, err_stop=0.0, record=True):
+        """ism_iterate_inner: returns (J history [n_iter, B], Err history [iters_done, B],
+        iters_done)."""
+        Jh = self._out((max(n_iter, 1), self.B), np.float64) if record else None
+        Eh = self._out((max(n_iter, 1), self.B), np.float64) if record else None
+        done = ct.c_int(0)
+        _check(lib().ism_iterate_inner(self._h, int(n_iter), int(n_inner), float(rho),
+                                       float(fid_stop), float(err_stop),
+                                       self._ptr(Jh) if Jh is not None else None,
+                                       self._ptr(Eh) if Eh is not None else None, ct.byref(done)),
+               "ism_iterate_inner")
+        if Jh is not None:
+            Jh = Jh[:n_iter]
+            Eh = Eh[:done.value]
+        return Jh, Eh, done.value
 
     def fidelity(self):
         J = self._out((self.B,), np.float64)

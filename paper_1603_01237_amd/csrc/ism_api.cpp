@@ -55,7 +55,7 @@ namespace ism {
 const char* const kKernelNames[KID_COUNT] = {
     "sp_params", "sp_assemble", "sp_boundary", "sp_slice", "check_finite",
     "gate_build", "gate_gemm", "gate_grad", "gate_boundary",
-    "gpe_sweep", "gpe_slice", "gpe_boundary", "sp_sweep"};
+    "gpe_sweep", "gpe_slice", "gpe_boundary", "sp_sweep", "err"};
 
 static hipEvent_t pool_get(ism_problem* p) {
     if (!p->event_pool.empty()) {
@@ -408,6 +408,23 @@ int slice_pass(ism_problem* p, int update, double rho, double* grad, bool use_ac
     return ISM_E_STATE;
 }
 
+// Per-step data at the current controls, for a slice pass that follows an update without a
+// boundary rebuild in between: Taylor / Neumann parameters (sparse path), step propagators and
+// in-slice products (gate path); the GPE slice kernel builds its steps from u itself.
+int refresh_steps(ism_problem* p) {
+    switch (p->path) {
+        case PATH_SPARSE: {
+            SpArgs a = sp_args(p, 0);
+            TimeScope ts(p, KID_SP_PARAMS);
+            ISM_TRY_HIP(sp_launch_params(a, p->h0norm, p->gnorm, p->precision, p->stream, p->flags));
+            return ISM_OK;
+        }
+        case PATH_GATE: return gate_refresh_pass(p);
+        case PATH_GPE: return ISM_OK;
+    }
+    return ISM_E_STATE;
+}
+
 // number of complex entries of one state (psi(T), chi(0)) per instance
 size_t state_elems(const ism_problem* p) {
     if (p->path == PATH_GATE) return (size_t)p->d * p->d;
@@ -610,7 +627,14 @@ int ism_gradient(ism_problem* p, double* grad) {
 
 int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double* J_hist,
                 int* iters_done) {
-    if (!p || n_iter < 0 || !std::isfinite(rho)) return ISM_E_ARG;
+    return ism_iterate_inner(p, n_iter, 1, rho, fid_stop, 0.0, J_hist, nullptr, iters_done);
+}
+
+int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, double fid_stop,
+                      double err_stop, double* J_hist, double* Err_hist, int* iters_done) {
+    if (!p || n_iter < 0 || n_inner < 1 || !std::isfinite(rho) || std::isnan(err_stop) ||
+        std::isnan(fid_stop))
+        return ISM_E_ARG;
     ISM_TRY_HIP(hipSetDevice(p->device));
     int st;
     const size_t need = (size_t)std::max(n_iter, 1) * p->B;
@@ -620,14 +644,23 @@ int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double*
         p->Jhist = nh;
         p->Jhist_cap = (int)need;
     }
+    const bool err_rule = err_stop > 0.0;
+    const bool want_err = err_rule || Err_hist != nullptr;
+    if (want_err && (size_t)p->Errhist_cap < need) {
+        double* nh = nullptr;
+        if ((st = dev_alloc(p, (void**)&nh, need * sizeof(double)))) return st;
+        p->Errhist = nh;
+        p->Errhist_cap = (int)need;
+    }
     std::vector<int> ones(p->B, 1);
     ISM_TRY_HIP(hipMemcpyAsync(p->active, ones.data(), p->B * sizeof(int), hipMemcpyHostToDevice,
                                p->stream));
     ISM_TRY_HIP(hipMemsetAsync(p->flags, 0, 4 * sizeof(int), p->stream));
-    const bool check_stop = fid_stop <= 1.0;
+    const bool check_stop = fid_stop <= 1.0 || err_rule;
     int done = 0;
     for (int k = 0; k < n_iter; ++k) {
         if (check_stop) ISM_TRY_HIP(hipMemsetAsync(p->flags + 1, 0, sizeof(int), p->stream));
+        // steps (a)-(b): boundaries and intermediate states at u^(k)
         if ((st = boundary_pass(p, p->Jhist + (size_t)k * p->B, fid_stop, true))) return st;
         if (check_stop) {
             int fl[4];
@@ -636,7 +669,20 @@ int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double*
             if (fl[0]) return ISM_E_NUMERIC;
             if (fl[1] == 0) break;
         }
-        if ((st = slice_pass(p, 1, rho, nullptr, true))) return st;
+        // steps (c)-(d): n_inner gradient steps on every slice problem, phi^(k) held
+        for (int l = 0; l < n_inner; ++l) {
+            if (l > 0 && (st = refresh_steps(p))) return st;
+            if ((st = slice_pass(p, 1, rho, nullptr, true))) return st;
+        }
+        // step (e): Err from the slice gradients at u^(k+1), phi^(k)
+        if (want_err) {
+            if ((st = refresh_steps(p))) return st;
+            if ((st = slice_pass(p, 0, 0.0, p->grad, true))) return st;
+            TimeScope ts(p, KID_ERR);
+            ISM_TRY_HIP(launch_err(p->grad, p->s, p->B, p->K, p->N, p->C, p->tau,
+                                   p->path != PATH_GPE, p->Errhist + (size_t)k * p->B, err_rule ? p->active : nullptr,
+                                   err_stop, p->flags, p->stream));
+        }
         done = k + 1;
     }
     int fl[4];
@@ -645,6 +691,9 @@ int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double*
     if (fl[0]) return ISM_E_NUMERIC;
     if (J_hist && n_iter > 0) {
         if ((st = copy_out(p, J_hist, p->Jhist, (size_t)n_iter * p->B * sizeof(double)))) return st;
+    }
+    if (Err_hist && done > 0) {
+        if ((st = copy_out(p, Err_hist, p->Errhist, (size_t)done * p->B * sizeof(double)))) return st;
     }
     if (iters_done) *iters_done = done;
     return ISM_OK;

@@ -78,7 +78,7 @@ struct BndArgs {
 enum KernelId {
     KID_SP_PARAMS = 0, KID_SP_ASSEMBLE, KID_SP_BOUNDARY, KID_SP_SLICE, KID_CHECK,
     KID_GATE_BUILD, KID_GATE_GEMM, KID_GATE_GRAD, KID_GATE_BOUNDARY,
-    KID_GPE_SWEEP, KID_GPE_SLICE, KID_GPE_BOUNDARY, KID_SP_SWEEP, KID_COUNT
+    KID_GPE_SWEEP, KID_GPE_SLICE, KID_GPE_BOUNDARY, KID_SP_SWEEP, KID_ERR, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -104,6 +104,12 @@ bool sp_tri_supported(int d);
 hipError_t sp_launch_slice(const SpArgs& a, int variant, int precision, hipStream_t st);
 hipError_t sp_launch_boundary(const BndArgs& a, hipStream_t st);
 hipError_t launch_check_finite(const double* x, size_t n, int* flag, hipStream_t st);
+// Err[b] of Algorithm 1 step (e) from the slice gradients g (B x K x C), which hold
+// beta_n grad J_n (beta_scaled = 1) or grad J_n (0); freezes active instances with
+// Err <= eta when eta > 0 and active is non-null
+hipError_t launch_err(const double* grad, const int* s, int B, int K, int N, int C, double tau,
+                      int beta_scaled, double* err, int* active, double eta, int* flags,
+                      hipStream_t st);
 
 }  // namespace ism
 
@@ -131,6 +137,8 @@ struct ism_problem {
     int* flags = nullptr;
     double* Jhist = nullptr;
     int Jhist_cap = 0;
+    double* Errhist = nullptr;
+    int Errhist_cap = 0;
     bool bvalid = false;
     bool tp_valid = false;   // Taylor parameters computed at least once
 

@@ -15,6 +15,9 @@ int read_flags(ism_problem* p, int* host_flags);
 int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism_options* o);
 int validate_common(int d, int C, double T, int K, int N, const ism_options* o);
 
+// per-step data at the current controls without a boundary rebuild (ism_api.cpp)
+int refresh_steps(ism_problem* p);
+
 // serving (ism_api.cpp): enqueue-only iteration steps, no host synchronisation
 int serve_begin(ism_problem* p, double fid_stop);
 int serve_chunk(ism_problem* p, int n, double rho, double fid_stop);
@@ -24,6 +27,8 @@ int gate_create(ism_problem* p, const double* H0, int h0_batched, const double* 
                 const double* psi0, const double* target);
 int gate_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active);
 int gate_slice_pass(ism_problem* p, int update, double rho, double* grad, bool use_active);
+// per-step propagators and in-slice products at the current controls (no boundary rebuild)
+int gate_refresh_pass(ism_problem* p);
 int gate_copy_state(ism_problem* p, double* out, int which_end);
 size_t gate_footprint_extra(int d, int C, int K, int N, int batch, int precision);
 

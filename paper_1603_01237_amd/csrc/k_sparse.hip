@@ -874,6 +874,48 @@ __global__ void k_check_finite(const double* x, size_t n, int* flag) {
     if (bad) atomicOr(flag, 1);
 }
 
+// Err of Algorithm 1, step (e), for instance blockIdx.x:
+//   Err = sum_n tau sum_{j in slice n} ||grad J_n|_j||_2,  grad J_n = g / beta_n,
+// g = beta_n grad J_n being what the slice kernels write (B x K x C, FP64) and
+// beta_n = K / (s_{n+1} - s_n); with beta_scaled == 0 the slice gradients are grad J_n
+// themselves (the BEC variant's slice problems carry no beta_n).  Each thread sums a fixed subset of steps in a fixed order
+// and the workgroup reduces in a fixed tree, so the result does not depend on timing.  An
+// active instance whose Err is <= eta (eta > 0) is frozen.
+__global__ __launch_bounds__(256) void k_err(const double* g, const int* s, int K, int N, int C,
+                                              double tau, int beta_scaled, double* err,
+                                              int* active, double eta, int* flags) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    const double* gb = g + (size_t)b * K * C;
+    double acc = 0.0;
+    for (int n = 0; n < N; ++n) {
+        const int j0 = s[n], j1 = s[n + 1];
+        const double w = beta_scaled ? tau * (double)(j1 - j0) / (double)K : tau;   // tau / beta_n
+        double part = 0.0;
+        for (int j = j0 + (int)threadIdx.x; j < j1; j += 256) {
+            double q = 0.0;
+            for (int c = 0; c < C; ++c) {
+                const double x = gb[(size_t)j * C + c];
+                q += x * x;
+            }
+            part += sqrt(q);
+        }
+        acc += w * part;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double e = red[0];
+        err[b] = e;
+        if (!(e < 1e300)) atomicOr(&flags[0], 1);
+        if (active && eta > 0.0 && active[b] && e <= eta) active[b] = 0;
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // variant table: (generators, entries per generator row, real generators)
 // ---------------------------------------------------------------------------------
@@ -1539,6 +1581,15 @@ hipError_t sp_launch_boundary(const BndArgs& a, hipStream_t st) {
         if (staged) launch_with_shm(k_sp_boundary<double, true>, dim3(a.B), dim3(threads), shmem, st, a);
         else launch_with_shm(k_sp_boundary<double, false>, dim3(a.B), dim3(threads), shmem, st, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_err(const double* grad, const int* s, int B, int K, int N, int C, double tau,
+                      int beta_scaled, double* err, int* active, double eta, int* flags,
+                      hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_err, dim3(B), dim3(256), 0, st, grad, s, K, N, C, tau, beta_scaled, err,
+                       active, eta, flags);
     return hipGetLastError();
 }
 
