@@ -154,14 +154,16 @@ def gpe_sweep_flops(prob):
 
 
 def other_workloads(stream, iters_gate=2, iters_gpe=2,
-                    which=("spins", "gate", "gpe", "rotor_cn")):
+                    which=("spins", "gate", "gpe", "rotor_cn", "rotor_inner")):
     """The paper's other benchmark shapes: the two-spin solve (latency), gate synthesis
     on MFMA, the condensate (sequential FFT sweeps), and the rotor batch with the
-    Crank-Nicolson step map."""
+    Crank-Nicolson step map and with several gradient steps per slice problem."""
     import problems
     out = {}
     if "rotor_cn" in which:
         out.update(_rotor_cn_workload(stream))
+    if "rotor_inner" in which:
+        out.update(_rotor_inner_workload(stream))
     if "spins" in which:
         out.update(_spins_workload(stream))
     if "gate" in which:
@@ -195,6 +197,39 @@ def _rotor_cn_workload(stream, steps=3):
                                    "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
                                    "frac": ach / PEAK_ALU}
     return {"rotor_cn": ent}
+
+
+def _rotor_inner_workload(stream, steps=3, ell=3):
+    """The benchmark's rotor batch with ell gradient steps per slice problem and the Err rule
+    (Algorithm 1 steps (c) and (e)): per iteration one assembly and boundary rebuild, ell
+    slice passes with updates and one slice pass for Err.  Each inner step is rho/ell, so
+    that an iteration moves the controls about as far as one plain step (ell steps of the
+    full rho overshoot on this problem)."""
+    import dataclasses
+    import problems
+    prob = problems.rotor()
+    prob = dataclasses.replace(prob, rho=prob.rho / ell)
+    B = prob.batch
+    r = {prec: run_gpu(prec, prob, steps, 1, stream, n_inner=ell) for prec in ("fp32", "fp64")}
+    passes = ell + 1
+    ent = {"workload": f"rotor batch, {ell} gradient steps of rho/{ell} per slice problem + Err: "
+                       f"{B} instances, d=21, K={prob.K}, N={prob.N}",
+           "ms_per_iteration": {k: v["seconds"] / steps * 1e3 for k, v in r.items()},
+           "slice_passes_per_iteration": passes,
+           "slice_steps_per_s": {k: B * 2 * prob.K * passes * steps / v["seconds"]
+                                 for k, v in r.items()},
+           "kernels_ms_per_iteration": {k: {n: t[1] / steps for n, t in v["kernels"].items()}
+                                        for k, v in r.items()},
+           "Err_mean_per_iteration": {k: v["Err_mean"] for k, v in r.items()},
+           "final_F_mean": {k: v["F_mean"] for k, v in r.items()}}
+    for prec, v in r.items():
+        launches, ms = v["kernels"]["sp_slice"]
+        fl = algorithmic_flops(prob, v["info"]["taylor_m"], v["info"]["taylor_S"], B)["sp_slice"]
+        ach = fl / (ms / launches * 1e-3)
+        ent[f"roofline_slice_{prec}"] = {"bound": "alu", "kernel": "sp_slice", "achieved": ach / 1e12,
+                                         "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
+                                         "frac": ach / PEAK_ALU}
+    return {"rotor_inner": ent}
 
 
 def _spins_workload(stream):
@@ -254,20 +289,28 @@ def _gpe_workload(stream, iters_gpe):
     return out
 
 
-def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp"):
+def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp", n_inner=None):
     """Warm-up iterations, controls reset to u0, then `steps` timed iterations (per-kernel
-    HIP events on the handle's stream when `timing`)."""
+    HIP events on the handle's stream when `timing`).  With n_inner, the iterations take
+    n_inner gradient steps per slice problem and evaluate Err (ism_iterate_inner)."""
     import torch
     from paper_1603_01237_amd import _lib
     h = _lib.from_problem(prob, precision=prec, stream=stream_ptr, step_map=step_map)
-    h.iterate(warmup, prob.rho, record=False)
+    if n_inner is None:
+        h.iterate(warmup, prob.rho, record=False)
+    else:
+        h.iterate_inner(warmup, n_inner, prob.rho, record=False)
     h.set_controls(prob.u0)
     torch.cuda.synchronize()
     h.set_timing(timing)
     h.kernel_times()
     torch.cuda.synchronize()
+    Eh = None
     t0 = time.perf_counter()
-    h.iterate(steps, prob.rho, record=False)
+    if n_inner is None:
+        h.iterate(steps, prob.rho, record=False)
+    else:
+        _, Eh, _ = h.iterate_inner(steps, n_inner, prob.rho, record=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = h.kernel_times()
@@ -275,8 +318,11 @@ def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp"):
     info = h.info()
     J, F = h.fidelity()
     h.close()
-    return {"seconds": t1 - t0, "kernels": kt, "info": info, "J_mean": float(J.mean()),
-            "F_mean": float(F.mean())}
+    out = {"seconds": t1 - t0, "kernels": kt, "info": info, "J_mean": float(J.mean()),
+           "F_mean": float(F.mean())}
+    if Eh is not None:
+        out["Err_mean"] = [float(e) for e in Eh.mean(axis=1)]
+    return out
 
 
 def cpu_baseline(prob, n_inst):
@@ -308,7 +354,7 @@ def main():
                     help="skip the two-spin, gate and condensate workloads")
     ap.add_argument("--serve", type=int, default=16,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
-    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn"],
+    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn", "rotor_inner"],
                     help="run only this secondary workload and print its figures (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the streaming kernel that scales the HBM byte counters")

@@ -168,3 +168,27 @@ def test_inner_argument_checks():
             with pytest.raises(_lib.IsmError) as e:
                 h.iterate_inner(**kw)
             assert e.value.code == _lib.ISM_E_ARG
+
+
+def test_inner_rotor_full_size_sampled():
+    """The benchmark's rotor batch (256 rotors, K=20000, N=128), one iteration with two
+    gradient steps per slice problem and Err, FP32 mixed and FP64; two instances checked
+    against the oracle.  FP64 bar as for the single-step path at this K (random-walk
+    rounding, 2e-14 sqrt(K))."""
+    from paper_1603_01237_amd import _lib
+    _say("case inner rotor full size")
+    p = problems.rotor()
+    tol64 = max(1e-12, 2e-14 * np.sqrt(p.K))
+    res = {}
+    for prec in ("fp32", "fp64"):
+        with _lib.from_problem(p, precision=prec) as h:
+            _, Eh, done = h.iterate_inner(1, 2, p.rho)
+            assert done == 1
+            res[prec] = (h.get_controls(), Eh[0])
+    for b in (0, 255):
+        r = _finite_ref(p, b, p.rho, 1, 2)
+        du = {k: _rel(v[0][b] - p.u0[b], r["u"] - p.u0[b]) for k, v in res.items()}
+        de = {k: abs(v[1][b] - r["Err"][0]) / r["Err"][0] for k, v in res.items()}
+        _say("instance", b, "update rel", du, "Err rel", de)
+        assert du["fp64"] <= tol64 and de["fp64"] <= tol64
+        assert du["fp32"] <= 1e-3 and de["fp32"] <= 1e-3
