@@ -12,6 +12,9 @@ Plain, slow, obviously-correct NumPy code in float64 / complex128:
   adjoint sweeps, the exact discrete gradient, the plain gradient method,
   and ISM with one gradient step per slice (Algorithm 1, Eq. (cible),
   Theorems 1 and 2, propagator assembling of Sec. 3).
+* ``oracle.density`` -- density-matrix (Liouville-von Neumann) problems of the
+  five-spin experiment of Sec. 4.A: conjugation step map, Hilbert-Schmidt inner
+  product, exact gradient, plain method and ISM.
 * ``oracle.gpe``    -- the 1-D Gross-Pitaevskii problem with Strang splitting
   (Eq. (OS)), its exact discrete adjoint and gradient, and the BEC variant of
   ISM (Sec. 4.C).

@@ -18,6 +18,8 @@ Workloads (shapes follow the paper's three benchmarks, Sec. 4):
 * ``spin_chain_gate`` / ``spin_chain_state``  open Ising chain with per-spin x/y
                   controls; gate synthesis towards a Haar-random unitary, or state
                   transfer |0..0> -> |1..1>.
+* ``spin5_density`` five coupled spin-1/2 in the density-matrix formalism with the
+                  coupling topology of Sec. 4.A, I_x^(1) -> I_x^(5).
 * ``gpe``         1-D Gross-Pitaevskii problem with a moving harmonic trap;
                   initial and target states are imaginary-time ground states
                   (Sec. 4.C uses ground states of the trap Hamiltonians as well).
@@ -33,7 +35,7 @@ import numpy as np
 __all__ = [
     "FiniteProblem", "GpeProblem", "pauli", "kron_chain", "haar_unitary",
     "spin2", "rotor", "rotor_cos_matrix", "rotor_target", "spin_chain_gate",
-    "spin_chain_state", "gpe", "gpe_grid", "gpe_ground_state", "serving_trace",
+    "spin_chain_state", "spin5_density", "spin_operators", "gpe", "gpe_grid", "gpe_ground_state", "serving_trace",
     "slice_starts",
 ]
 
@@ -44,7 +46,8 @@ class FiniteProblem:
 
     H0 has shape (batch, d, d) (one per instance) or (d, d) (shared);
     Hc has shape (C, d, d); psi0/target have shape (d,) for state transfer or
-    (d, d) for gate synthesis (kind == "gate"); u0 has shape (batch, K, C).
+    (d, d) for gate synthesis (kind == "gate") and for density matrices (kind == "density");
+    u0 has shape (batch, K, C).
     alpha is an array of shape (K,) (penalty weight per step, Eq. for J).
     """
     name: str
@@ -256,6 +259,44 @@ def spin_chain_state(seed: int, n: int, T: float, K: int, N: int, iters: int = 2
     u0 = 0.1 + rng.uniform(-0.01, 0.01, size=(1, K, 2 * n))
     return FiniteProblem("spin_chain_state", H0, Hc, psi0, tgt, T, K, N, u0, np.zeros(K),
                          rho, iters, meta={"J": J})
+
+
+# ----------------------------------------------------------------------------
+# five coupled spins, density matrices (Sec. 4.A)
+# ----------------------------------------------------------------------------
+
+SPIN5_BONDS = ((0, 1), (0, 2), (1, 2), (1, 4), (2, 3))   # J12, J13, J23, J25, J34 (0-based)
+
+
+def spin_operators(n: int):
+    """I_x^(k), I_y^(k), I_z^(k) = sigma/2 on spin k of an n-spin register."""
+    p = pauli()
+    return ([0.5 * embed(p["x"], k, n) for k in range(n)],
+            [0.5 * embed(p["y"], k, n) for k in range(n)],
+            [0.5 * embed(p["z"], k, n) for k in range(n)])
+
+
+def spin5_density(seed: int = 1005, K: int = 2 ** 15, N: int = 8, Jp: float = 140.0,
+                  T: Optional[float] = None, u_amp: float = 100.0, iters: int = 5,
+                  rho: float = 1e4) -> FiniteProblem:
+    """Five coupled spins: H0 = 2 pi Jp sum_{bonds} I_z^(a) I_z^(b) over the bonds 1-2, 1-3,
+    2-3, 2-5, 3-4; controls u_x^k I_x^(k) + u_y^k I_y^(k) in the order (x1, y1, ..., x5, y5);
+    density matrices rho(0) = I_x^(1), rho_f = I_x^(5); alpha = 0; constant step 1e4.
+    T defaults to 10/Jp (the printed T = Jp/10 is read as 10/Jp); the paper's step count is
+    2^15.  u0 ~ U(-u_amp, u_amp) (rad per unit time)."""
+    Ix, Iy, Iz = spin_operators(5)
+    H0 = np.zeros((32, 32), dtype=np.complex128)
+    for a, b in SPIN5_BONDS:
+        H0 += 2 * math.pi * Jp * (Iz[a] @ Iz[b])
+    Hc = []
+    for k in range(5):
+        Hc.append(Ix[k])
+        Hc.append(Iy[k])
+    T = 10.0 / Jp if T is None else T
+    rng = np.random.default_rng(seed)
+    u0 = rng.uniform(-u_amp, u_amp, size=(1, K, 10))
+    return FiniteProblem("spin5_density", H0, np.stack(Hc), Ix[0], Ix[4], T, K, N, u0,
+                         np.zeros(K), rho, iters, kind="density", meta={"Jp": Jp})
 
 
 # ----------------------------------------------------------------------------

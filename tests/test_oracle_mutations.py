@@ -167,3 +167,33 @@ def test_mutation_inner_step_without_beta(monkeypatch):
     monkeypatch.setattr(O, "subproblem_gradient", unscaled)
     bad = O.ism_iterate_inner(N=4, ell=1, **kw)
     assert np.max(np.abs(bad["u"] - plain["u"])) > 1e-3
+
+
+def test_mutation_density_one_sided_adjoint(monkeypatch):
+    """An adjoint propagated as U^+ lambda (state rule) instead of U^+ lambda U is caught by
+    the Liouville-space vectorisation pin."""
+    from oracle import density as D
+    rng = np.random.default_rng(4)
+    d, K, T = 3, 8, 0.7
+    A = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)); H0 = A + A.conj().T
+    B = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)); Hc = np.stack([B + B.conj().T])
+    R0 = np.diag([1.0, -0.5, 0.2]).astype(complex); Rf = np.roll(R0, 1, axis=0) + np.roll(R0, 1, axis=0).T
+    u = rng.uniform(-1, 1, size=(K, 1)); al = np.zeros(K)
+
+    def lv(H):
+        return np.kron(H, np.eye(d)) - np.kron(np.eye(d), H.T)
+
+    def err():
+        g, *_ = D.gradient(H0, Hc, R0, Rf, u, T, al)
+        gv, *_ = O.gradient(lv(H0), np.stack([lv(Hc[0])]), R0.reshape(-1), Rf.reshape(-1), u, T, al)
+        return np.max(np.abs(g - gv))
+    assert err() <= 1e-11
+
+    def one_sided(Us, target):
+        out = [None] * (len(Us) + 1)
+        out[-1] = np.array(target, dtype=np.complex128)
+        for j in range(len(Us) - 1, -1, -1):
+            out[j] = Us[j].conj().T @ out[j + 1]
+        return out
+    monkeypatch.setattr(D, "backward", one_sided)
+    assert err() > 1e-3
