@@ -66,8 +66,19 @@ typedef enum ism_precision {
 
 typedef enum ism_kind {
     ISM_STATE = 0,          /* psi0, target are d-vectors; <a|b> = sum conj(a) b */
-    ISM_GATE = 1            /* psi0, target are d x d matrices (evolution operators, Sec. 2
+    ISM_GATE = 1,           /* psi0, target are d x d matrices (evolution operators, Sec. 2
                                remark); <A|B> = Tr(A^dagger B)/d */
+    ISM_DENSITY = 2         /* psi0, target are Hermitian d x d operators evolving as
+                               i d/dt rho = [H, rho] (the density-matrix formalism of the
+                               five-spin run, Sec. 4.A): one step is rho <- U_j rho U_j^dagger,
+                               <A|B> = Tr(A^dagger B), J = Re<rho(T)|rho_f> - penalty,
+                               F = |<rho(T)|rho_f>|^2 / (<rho_0|rho_0><rho_f|rho_f>), gradient
+                               Im Tr(Hhat_{c,j} [rho_j, lambda_j]).  Dense (MFMA) path, batch 1,
+                               exponential step map only.  On the dense path (ISM_GATE and
+                               ISM_DENSITY) the exact gradient's series is bounded: steps with
+                               2 tau ||H_j - s||_inf above 1.46 (FP64) or 2.0 (FP32 mixed) make
+                               ism_gradient / ism_iterate return ISM_E_UNSUPPORTED (s: the
+                               midpoint of the diagonal of H0). */
 } ism_kind;
 
 typedef enum ism_step_map {
@@ -108,11 +119,12 @@ void ism_default_options(ism_options* opt);
  * of Sec. 2; time grid of Sec. 3).
  *   out     : receives the new handle.
  *   d       : Hilbert-space dimension, 1 <= d <= 256 for state problems (ISM_STATE),
- *             d <= 256 for gate problems (ISM_GATE).
+ *             d <= 256 for gate (ISM_GATE) and density-matrix (ISM_DENSITY) problems.
  *   n_ctrl  : number of controls C >= 1.
  *   H0      : d x d complex (or B x d x d if opt->h0_batched), Hermitian to 1e-12 relative.
  *   Hc      : C x d x d complex, contiguous, each Hermitian.
- *   psi0    : initial state: d complex (ISM_STATE) or d x d (ISM_GATE); shared by all instances.
+ *   psi0    : initial state: d complex (ISM_STATE) or d x d (ISM_GATE, ISM_DENSITY; Hermitian
+ *             for ISM_DENSITY); shared by all instances.
  *   target  : target psi_f, same shape as psi0.
  *   T       : final time > 0.
  *   K       : number of time steps >= 1 (tau = T/K).

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libism.so")
 
 ISM_OK, ISM_E_ARG, ISM_E_NOMEM, ISM_E_DEVICE, ISM_E_STATE, ISM_E_NUMERIC, ISM_E_UNSUPPORTED, ISM_E_BUDGET = range(8)
 FP64, FP32_MIXED = 0, 1
-STATE, GATE = 0, 1
+STATE, GATE, DENSITY = 0, 1, 2
+KINDS = {"state": STATE, "gate": GATE, "density": DENSITY}
 STEP_EXP, STEP_CN = 0, 1
 STEP_MAPS = {"exp": STEP_EXP, "cn": STEP_CN}
 PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
@@ -195,8 +196,8 @@ class Problem:
         H0 = _as_c128(H0)
         if h0_batched and H0.shape != (batch, d, d):
             raise ValueError("batched H0 must have shape (batch, d, d)")
-        kind_i = GATE if kind == "gate" else STATE
-        sshape = (d, d) if kind_i == GATE else (d,)
+        kind_i = KINDS[kind] if isinstance(kind, str) else int(kind)
+        sshape = (d, d) if kind_i in (GATE, DENSITY) else (d,)
         psi0 = _as_c128(psi0, sshape)
         target = _as_c128(target, sshape)
         o = Options()
@@ -424,7 +425,7 @@ class Server:
             if prob.H0.ndim == 3 and prob.H0.shape[0] != 1:
                 raise ValueError("a served request holds one instance")
             r.model = REQ_FINITE
-            r.kind = GATE if prob.kind == "gate" else STATE
+            r.kind = KINDS[prob.kind]
             r.d, r.n_ctrl = prob.Hc.shape[-1], prob.Hc.shape[0]
             r.H0 = ptr(prob.H0.reshape(r.d, r.d), np.complex128)
             r.Hc = ptr(prob.Hc, np.complex128)

@@ -173,7 +173,7 @@ int validate_common(int d, int C, double T, int K, int N, const ism_options* o) 
     if (d < 1 || C < 1 || K < 1 || N < 1 || N > K) return ISM_E_ARG;
     if (!(T > 0.0) || !std::isfinite(T)) return ISM_E_ARG;
     if (o->batch < 1 || (o->precision != ISM_FP64 && o->precision != ISM_FP32_MIXED)) return ISM_E_ARG;
-    if (o->kind != ISM_STATE && o->kind != ISM_GATE) return ISM_E_ARG;
+    if (o->kind != ISM_STATE && o->kind != ISM_GATE && o->kind != ISM_DENSITY) return ISM_E_ARG;
     if (o->step_map != ISM_STEP_EXP && o->step_map != ISM_STEP_CN) return ISM_E_ARG;
     if (o->alpha) {
         if (o->alpha_len != 1 && o->alpha_len != K) return ISM_E_ARG;
@@ -540,16 +540,18 @@ int ism_problem_create(ism_problem** out, int d, int n_ctrl, const double* H0, c
         if (!finite_all(Hc + (size_t)c * 2 * d * d, (size_t)2 * d * d) ||
             !hermitian(Hc + (size_t)c * 2 * d * d, d))
             return ISM_E_ARG;
-    const size_t se = o.kind == ISM_GATE ? (size_t)d * d : (size_t)d;
+    const bool dense = o.kind == ISM_GATE || o.kind == ISM_DENSITY;
+    const size_t se = dense ? (size_t)d * d : (size_t)d;
     if (!finite_all(psi0, 2 * se) || !finite_all(target, 2 * se)) return ISM_E_ARG;
+    if (o.kind == ISM_DENSITY && (!hermitian(psi0, d) || !hermitian(target, d))) return ISM_E_ARG;
 
     ism_problem* p = new (std::nothrow) ism_problem();
     if (!p) return ISM_E_NOMEM;
     st = common_setup(p, d, n_ctrl, T, K, N, &o);
     if (!st) {
-        if (o.kind == ISM_GATE && p->step_cn) {
+        if (dense && p->step_cn) {
             st = ISM_E_UNSUPPORTED;
-        } else if (o.kind == ISM_GATE) {
+        } else if (dense) {
             p->path = PATH_GATE;
             st = gate_create(p, H0, o.h0_batched, Hc, psi0, target);
         } else {
@@ -784,7 +786,8 @@ size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kin
         return bytes + 4 * n * 8 + 2 * n * 16 +
                gpe_footprint_extra(n, K, N, batch, precision);
     }
-    if (kind == ISM_GATE) return bytes + gate_footprint_extra(d, n_ctrl, K, N, batch, precision);
+    if (kind == ISM_GATE || kind == ISM_DENSITY)
+        return bytes + gate_footprint_extra(d, n_ctrl, K, N, batch, precision);
     const size_t dd = d;
     bytes += 3 * B * (N + 1) * dd * 16;              // Psi, Lam, phi
     bytes += B * N * dd * dd * 2 * rs;               // slice propagators

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
     const int i0 = (blockIdx.x / tilesN) * GT, j0 = (blockIdx.x % tilesN) * GT;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    const bool hA = e.flags & 1, hB = e.flags & 2;
+    const bool hA = e.flags & 1, hB = e.flags & 2, addB = e.flags & 4;
     typename Acc<R>::T cr[2][2], ci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -160,8 +160,14 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
                               (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
                 const int j = j0 + wc + b * 16 + (lane & 15);
                 const long long o = (long long)i * g.ldc + j;
-                Cm[o] = cr[a][b][v];
-                Cm[o + g.pc] = ci[a][b][v];
+                if (addB) {                       // C = A B + B (square, B not transposed)
+                    const long long ob = (long long)i * g.ldb + j;
+                    Cm[o] = cr[a][b][v] + Bm[ob];
+                    Cm[o + g.pc] = ci[a][b][v] + Bm[ob + g.pb];
+                } else {
+                    Cm[o] = cr[a][b][v];
+                    Cm[o + g.pc] = ci[a][b][v];
+                }
             }
 }
 
@@ -285,9 +291,25 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
                 xr = yr;
                 xi = yi;
             }
+            // stored as D_j = U_j - I: at small tau U_j is close to I, and rounding I + delta
+            // to FP32 would make the same error at every step of a slice
+            if (r == c) xr -= 1.0;
             U[o] = (R)xr;
             U[o + plane] = (R)xi;
         }
+    }
+}
+
+// First propagator of every slice: P_{s_n} = I + D_{s_n} (blockIdx.y = n).
+template <typename R>
+__global__ void k_gate_first(const R* D, R* P, const int* s, int dp) {
+    const long long plane = (long long)dp * dp;
+    const long long base = (long long)s[blockIdx.y] * 2 * plane;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * plane;
+         e += (long long)gridDim.x * blockDim.x) {
+        R v = D[base + e];
+        if (e < plane && e / dp == e % dp) v += R(1);
+        P[base + e] = v;
     }
 }
 
@@ -311,9 +333,12 @@ __device__ constexpr WabTable kWab = make_wab();
 
 // Per (step, block of CBW columns): partial sums over rows and columns of
 // Im <y_k| Hhat_c |x_k> for every control c, in FP64.  MK bounds the Krylov order.
+// A step whose series, cut at MK terms, leaves a remainder bound above 1e-13 (FP64) or 1e-7
+// (FP32) sets bit 1 of flags[0] (reported as unsupported, never truncated silently):
+// 2 tau ||H_j - s||_inf above 1.46 in FP64 or 2.0 in FP32.
 template <typename R, int MK, int WT>
 __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
-                                                   int ldxy, double* gpart, int ncb) {
+                                                   int ldxy, double* gpart, int ncb, int* flags) {
     // LDS: per-row gradient accumulators of every control; Krylov vectors (tau H')^b x,
     // b = 0..MK, as re/im planes; a double buffer for the Krylov vectors of y; the
     // per-wavefront partial sums of the final reduction.
@@ -337,6 +362,7 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
             ++m;
             t = t * x / (m + 2);
         }
+        if (t > (sizeof(R) == 8 ? 1e-13 : 1e-7) && r == 0 && cb == 0) atomicOr(flags, 2);
     }
     // row r of tau (H_j - s) on the union pattern
     R hvr[WT], hvi[WT];
@@ -460,9 +486,12 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
     }
 }
 // g_{j,c} = beta_n (1/d) sum_cb gpart - alpha_j u_{j,c}; update or write the gradient.
-__global__ void k_gate_grad_finish(const double* gpart, int ncb, int K, int N, int C, int d,
-                                   const int* s, double* u, const double* alpha, double* grad,
-                                   double rho, int update, const int* active) {
+// gscale: 1/d for evolution operators (<A|B> = Tr(A^+ B)/d); 2 for density matrices, where
+// Im Tr(Hhat [rho_j, lambda_j]) = 2 Im Tr(Y_j^+ Hhat X_j) with X_j = P_{j-1} phi_n and
+// Y_j = P_{j-1} M_n^+ phi_{n+1} M_n.
+__global__ void k_gate_grad_finish(const double* gpart, int ncb, int K, int N, int C,
+                                   double gscale, const int* s, double* u, const double* alpha,
+                                   double* grad, double rho, int update, const int* active) {
     if (active && active[0] == 0) update = 0;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= K * C) return;
@@ -477,7 +506,7 @@ __global__ void k_gate_grad_finish(const double* gpart, int ncb, int K, int N, i
     double acc = 0.0;
     for (int cb = 0; cb < ncb; ++cb) acc += gpart[((size_t)j * ncb + cb) * C + c];
     const double uu = u[idx];
-    const double g = beta * acc / d - (alpha ? alpha[j] : 0.0) * uu;
+    const double g = beta * acc * gscale - (alpha ? alpha[j] : 0.0) * uu;
     if (grad) grad[idx] = g;
     if (update) u[idx] = fma(rho, g, uu);
 }
@@ -522,10 +551,12 @@ __global__ void k_gate_phi(const double* Psi, const double* Lam, double* phi, R*
     }
 }
 
-// J = Re Tr(W^+ Psi_N)/d, F = |Tr(W^+ Psi_N)|^2/d^2 (one block), penalty from u.
-__global__ void k_gate_fid(const double* PsiN, const double* W, int d, int dp, const double* u,
-                           const double* alpha, int K, int C, double tau, double* J, double* F,
-                           double* Jhist, int* active, double fid_stop, int* flags) {
+// z = js Tr(W^+ Psi_N): J = Re z - penalty, F = fs |z|^2 (one block).  Evolution operators:
+// js = 1/d, fs = 1; density matrices: js = 1, fs = 1/(<rho_0|rho_0><rho_f|rho_f>).
+__global__ void k_gate_fid(const double* PsiN, const double* W, int d, int dp, double js,
+                           double fs, const double* u, const double* alpha, int K, int C,
+                           double tau, double* J, double* F, double* Jhist, int* active,
+                           double fid_stop, int* flags) {
     __shared__ double red[3][256];
     const int t = threadIdx.x;
     const long long plane = (long long)dp * dp;
@@ -550,9 +581,9 @@ __global__ void k_gate_fid(const double* PsiN, const double* W, int d, int dp, c
         __syncthreads();
     }
     if (t == 0) {
-        const double a = red[0][0] / d, b = red[1][0] / d;
+        const double a = red[0][0] * js, b = red[1][0] * js;
         const double Jv = a - 0.5 * tau * red[2][0];
-        const double Fv = a * a + b * b;
+        const double Fv = (a * a + b * b) * fs;
         J[0] = Jv;
         F[0] = Fv;
         if (Jhist) Jhist[0] = Jv;

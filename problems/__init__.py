@@ -283,7 +283,9 @@ def spin5_density(seed: int = 1005, K: int = 2 ** 15, N: int = 8, Jp: float = 14
     2-3, 2-5, 3-4; controls u_x^k I_x^(k) + u_y^k I_y^(k) in the order (x1, y1, ..., x5, y5);
     density matrices rho(0) = I_x^(1), rho_f = I_x^(5); alpha = 0; constant step 1e4.
     T defaults to 10/Jp (the printed T = Jp/10 is read as 10/Jp); the paper's step count is
-    2^15.  u0 ~ U(-u_amp, u_amp) (rad per unit time)."""
+    2^15.  u0: a constant field u_amp on the five x controls plus U(-u_amp/10, u_amp/10) on
+    every control (rad per unit time), so that the transfer and the gradient start far from
+    zero."""
     Ix, Iy, Iz = spin_operators(5)
     H0 = np.zeros((32, 32), dtype=np.complex128)
     for a, b in SPIN5_BONDS:
@@ -294,7 +296,8 @@ def spin5_density(seed: int = 1005, K: int = 2 ** 15, N: int = 8, Jp: float = 14
         Hc.append(Iy[k])
     T = 10.0 / Jp if T is None else T
     rng = np.random.default_rng(seed)
-    u0 = rng.uniform(-u_amp, u_amp, size=(1, K, 10))
+    u0 = rng.uniform(-0.1 * u_amp, 0.1 * u_amp, size=(1, K, 10))
+    u0[:, :, 0::2] += u_amp
     return FiniteProblem("spin5_density", H0, np.stack(Hc), Ix[0], Ix[4], T, K, N, u0,
                          np.zeros(K), rho, iters, kind="density", meta={"Jp": Jp})
 

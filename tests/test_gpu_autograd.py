@@ -38,10 +38,10 @@ def test_gradcheck_gate_fp64():
     from paper_1603_01237_amd.autograd import ISMObjective
     _say("case gradcheck gate")
     rng = np.random.default_rng(4)
-    base = problems.spin2(K=5, N=2)
+    base = problems.spin2(K=12, N=3)
     W = problems.haar_unitary(4, rng)
-    p = problems.FiniteProblem("g", base.H0, base.Hc, np.eye(4, dtype=complex), W, 1.0, 5, 2,
-                               rng.uniform(-1, 1, (1, 5, 2)), np.zeros(5), 0.5, 1, kind="gate")
+    p = problems.FiniteProblem("g", base.H0, base.Hc, np.eye(4, dtype=complex), W, 1.0, 12, 3,
+                               rng.uniform(-1, 1, (1, 12, 2)), np.zeros(12), 0.5, 1, kind="gate")
     h = _handle(p)
     u = torch.tensor(p.u0, dtype=torch.float64, device="cuda", requires_grad=True)
     assert torch.autograd.gradcheck(lambda x: ISMObjective.apply(x, h), (u,), eps=1e-6,
