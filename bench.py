@@ -137,13 +137,15 @@ PEAK_MFMA = {"fp32": 157.3e12, "fp64": 78.6e12}    # dense MFMA, v_mfma_*_16x16x
 PEAK_CU_FP64 = 78.6e12 / 256                       # one CU (a sequential sweep is one workgroup)
 
 
-def gate_gemm_flops(prob, dp):
-    """MFMA work of one ISM iteration of the gate path (path precision), 8 d^3 flops per
-    complex d x d x d product: the assembly chain P_j = U_j P_{j-1} (K - N products), the
-    slice right-hand sides M_n^+ phi_{n+1} (N) and [X_j | Y_j] = P_{j-1} [phi_n | .]
-    (K - N products of twice the width)."""
+def gate_gemm_flops(prob, d):
+    """Algorithmic MFMA work of one ISM iteration of the dense path (path precision), 8 d^3
+    flops per complex d x d x d product: the assembly chain P_j = U_j P_{j-1} (K - N
+    products), the slice right-hand sides M_n^+ phi_{n+1} (N; density matrices: N more for
+    the right factor M_n) and [X_j | Y_j] = P_{j-1} [phi_n | .] (K - N products of twice the
+    width).  d is the unpadded dimension (the kernels pad to a multiple of 64)."""
     K, N = prob.K, prob.N
-    return 8.0 * dp ** 3 * (3 * K - 2 * N)
+    extra = N if getattr(prob, "kind", "") == "density" else 0
+    return 8.0 * d ** 3 * (3 * K - 2 * N + extra)
 
 
 def gpe_sweep_flops(prob):
@@ -154,7 +156,7 @@ def gpe_sweep_flops(prob):
 
 
 def other_workloads(stream, iters_gate=2, iters_gpe=2,
-                    which=("spins", "gate", "gpe", "rotor_cn", "rotor_inner")):
+                    which=("spins", "gate", "gpe", "rotor_cn", "rotor_inner", "density")):
     """The paper's other benchmark shapes: the two-spin solve (latency), gate synthesis
     on MFMA, the condensate (sequential FFT sweeps), and the rotor batch with the
     Crank-Nicolson step map and with several gradient steps per slice problem."""
@@ -164,6 +166,8 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2,
         out.update(_rotor_cn_workload(stream))
     if "rotor_inner" in which:
         out.update(_rotor_inner_workload(stream))
+    if "density" in which:
+        out.update(_density_workload(stream))
     if "spins" in which:
         out.update(_spins_workload(stream))
     if "gate" in which:
@@ -230,6 +234,37 @@ def _rotor_inner_workload(stream, steps=3, ell=3):
                                          "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
                                          "frac": ach / PEAK_ALU}
     return {"rotor_inner": ent}
+
+
+def _density_workload(stream, steps=2):
+    """The five-spin density-matrix run (Sec. 4.A, Liouville-von Neumann form, K = 2^15) on
+    the dense MFMA path: one ISM iteration per step at N = 1, 2, 4, 8 slices (FP32 mixed) and
+    at N = 8 in FP64; the efficiency t(1) / (N t(N)) is the single-GPU counterpart of the
+    paper's parallel-efficiency table."""
+    import problems
+    p = problems.spin5_density()
+    out = {"workload": f"five spins, density matrices (d=32), K={p.K}, one ISM iteration per "
+                       f"step, constant step {p.rho:g}",
+           "ms_per_iteration": {}, "kernels_ms_per_iteration": {}}
+    for N in (1, 2, 4, 8):
+        q = problems.spin5_density(N=N)
+        r = run_gpu("fp32", q, steps, 1, stream)
+        out["ms_per_iteration"][f"fp32_N{N}"] = r["seconds"] / steps * 1e3
+        out["kernels_ms_per_iteration"][f"fp32_N{N}"] = {n: t[1] / steps for n, t in r["kernels"].items()}
+        if N == 8:
+            out["final_J_fp32_N8"] = r["J_mean"]
+            launches, ms = r["kernels"]["gate_gemm"]
+            ach = gate_gemm_flops(q, q.d) * steps / (ms * 1e-3)
+            out["roofline_fp32_N8"] = {"bound": "mfma", "kernel": "gate_gemm (all batched GEMMs)",
+                                       "achieved": ach / 1e12, "peak": PEAK_MFMA["fp32"] / 1e12,
+                                       "unit": "TFLOP/s", "frac": ach / PEAK_MFMA["fp32"]}
+    r = run_gpu("fp64", p, steps, 1, stream)
+    out["ms_per_iteration"]["fp64_N8"] = r["seconds"] / steps * 1e3
+    out["kernels_ms_per_iteration"]["fp64_N8"] = {n: t[1] / steps for n, t in r["kernels"].items()}
+    t = out["ms_per_iteration"]
+    out["efficiency_fp32"] = {f"N{N}": t["fp32_N1"] / (N * t[f"fp32_N{N}"]) for N in (1, 2, 4, 8)}
+    out["useful_matrix_steps_per_s"] = {k: 2 * p.K / (v * 1e-3) for k, v in t.items()}
+    return {"spin5_density": out}
 
 
 def _spins_workload(stream):
@@ -354,7 +389,7 @@ def main():
                     help="skip the two-spin, gate and condensate workloads")
     ap.add_argument("--serve", type=int, default=16,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
-    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn", "rotor_inner"],
+    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn", "rotor_inner", "density"],
                     help="run only this secondary workload and print its figures (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the streaming kernel that scales the HBM byte counters")

@@ -300,6 +300,116 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
     }
 }
 
+// Assembly chain of one slice in one workgroup, for dp = 64 (blockIdx.x = n):
+// P_{s_n} = I + D_{s_n}, then P_j = P_{j-1} + D_j P_{j-1} for the rest of the slice.
+// P_{j-1} stays in LDS between steps and D_{j+1} is fetched into registers while step j
+// runs on MFMA, so a slice costs one pass over its D_j and no launch per step.  LDS:
+// Ds[p][k][i] = D_j[i][k] and Ps[p][k][c] = P_{j-1}[k][c], p = re/im, rows padded to 65.
+constexpr int CH_LD = GT + 1;
+constexpr int CH_PL = GT * CH_LD;
+
+template <typename R>
+static size_t gate_chain_shmem() {
+    return (size_t)4 * CH_PL * sizeof(R);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gate_chain64(const R* D, R* P, const int* s) {
+    extern __shared__ unsigned char smem_raw[];
+    R* Ds = reinterpret_cast<R*>(smem_raw);
+    R* Ps = Ds + 2 * CH_PL;
+    constexpr long long plane = (long long)GT * GT, mat = 2 * plane;
+    constexpr int PER = (int)(mat / 256);            // matrix entries per thread
+    const int n = blockIdx.x;
+    const int j0 = s[n], j1 = s[n + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    R pre[PER];
+    // entry e = t + 256 q of a planar matrix: plane e / 4096, row (e % 4096) / 64, column e % 64
+    {
+        const R* src = D + (long long)j0 * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[t + 256 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q, p = e >> 12, r = (e >> 6) & 63, c = e & 63;
+        const R v = pre[q] + ((p == 0 && r == c) ? R(1) : R(0));
+        Ps[p * CH_PL + r * CH_LD + c] = v;
+        P[(long long)j0 * mat + e] = v;
+    }
+    if (j0 + 1 < j1) {
+        const R* src = D + (long long)(j0 + 1) * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[t + 256 * q];
+    }
+    __syncthreads();
+    for (int j = j0 + 1; j < j1; ++j) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e >> 12, r = (e >> 6) & 63, c = e & 63;
+            Ds[p * CH_PL + c * CH_LD + r] = pre[q];
+        }
+        __syncthreads();
+        if (j + 1 < j1) {
+            const R* src = D + (long long)(j + 1) * mat;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) pre[q] = src[t + 256 * q];
+        }
+        typename Acc<R>::T cr[2][2], ci[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0;
+#pragma unroll 4
+        for (int kk = 0; kk < GT; kk += 4) {
+            const int kr = kk + (lane >> 4), li = lane & 15;
+            R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                ar[a] = Ds[kr * CH_LD + wr + a * 16 + li];
+                ai[a] = Ds[CH_PL + kr * CH_LD + wr + a * 16 + li];
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                br[b] = Ps[kr * CH_LD + wc + b * 16 + li];
+                bi[b] = Ps[CH_PL + kr * CH_LD + wc + b * 16 + li];
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cr[a][b] = mfma16(ar[a], br[b], cr[a][b]);
+                    cr[a][b] = mfma16(-ai[a], bi[b], cr[a][b]);
+                    ci[a][b] = mfma16(ar[a], bi[b], ci[a][b]);
+                    ci[a][b] = mfma16(ai[a], br[b], ci[a][b]);
+                }
+        }
+        __syncthreads();                  // every wavefront is done with Ds and Ps
+        R* dst = P + (long long)j * mat;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = wr + a * 16 +
+                                  (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+                    const int c = wc + b * 16 + (lane & 15);
+                    const int o = i * CH_LD + c;
+                    const R nr = cr[a][b][v] + Ps[o];
+                    const R ni = ci[a][b][v] + Ps[CH_PL + o];
+                    Ps[o] = nr;
+                    Ps[CH_PL + o] = ni;
+                    dst[i * GT + c] = nr;
+                    dst[plane + i * GT + c] = ni;
+                }
+        __syncthreads();                  // P_j complete in LDS before the next step
+    }
+}
+
 // First propagator of every slice: P_{s_n} = I + D_{s_n} (blockIdx.y = n).
 template <typename R>
 __global__ void k_gate_first(const R* D, R* P, const int* s, int dp) {
