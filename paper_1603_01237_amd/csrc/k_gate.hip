@@ -410,6 +410,103 @@ __global__ __launch_bounds__(256) void k_gate_chain64(const R* D, R* P, const in
     }
 }
 
+// The same chain for d <= 32: only the leading 32 x 32 block of every P_j is formed (one
+// 16 x 16 MFMA block per wavefront, a quarter of the columns of the 64 x 64 tile and an
+// eighth of its work); the rest of each P_j is the identity, written once by
+// k_gate_pad_identity, and the rest of each D_j is zero.
+constexpr int C32_LD = 33;
+constexpr int C32_PL = 32 * C32_LD;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gate_chain32(const R* D, R* P, const int* s) {
+    __shared__ R Ds[2 * C32_PL];   // Ds[p][k][i] = D_j[i][k]
+    __shared__ R Ps[2 * C32_PL];   // Ps[p][k][c] = P_{j-1}[k][c]
+    constexpr long long plane = (long long)GT * GT, mat = 2 * plane;
+    constexpr int PER = 2 * 32 * 32 / 256;
+    const int n = blockIdx.x;
+    const int j0 = s[n], j1 = s[n + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+    R pre[PER];
+    // entry e = t + 256 q of the leading block: plane e / 1024, row (e % 1024) / 32, column e % 32
+    auto gidx = [](int e) -> long long {
+        return (long long)(e >> 10) * plane + ((e >> 5) & 31) * GT + (e & 31);
+    };
+    {
+        const R* src = D + (long long)j0 * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[gidx(t + 256 * q)];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q, p = e >> 10, r = (e >> 5) & 31, c = e & 31;
+        const R v = pre[q] + ((p == 0 && r == c) ? R(1) : R(0));
+        Ps[p * C32_PL + r * C32_LD + c] = v;
+        P[(long long)j0 * mat + gidx(e)] = v;
+    }
+    if (j0 + 1 < j1) {
+        const R* src = D + (long long)(j0 + 1) * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[gidx(t + 256 * q)];
+    }
+    __syncthreads();
+    for (int j = j0 + 1; j < j1; ++j) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e >> 10, r = (e >> 5) & 31, c = e & 31;
+            Ds[p * C32_PL + c * C32_LD + r] = pre[q];
+        }
+        __syncthreads();
+        if (j + 1 < j1) {
+            const R* src = D + (long long)(j + 1) * mat;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) pre[q] = src[gidx(t + 256 * q)];
+        }
+        typename Acc<R>::T cr, ci;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cr[v] = ci[v] = 0;
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 4) {
+            const int kr = kk + (lane >> 4), li = lane & 15;
+            const R ar = Ds[kr * C32_LD + wr + li], ai = Ds[C32_PL + kr * C32_LD + wr + li];
+            const R br = Ps[kr * C32_LD + wc + li], bi = Ps[C32_PL + kr * C32_LD + wc + li];
+            cr = mfma16(ar, br, cr);
+            cr = mfma16(-ai, bi, cr);
+            ci = mfma16(ar, bi, ci);
+            ci = mfma16(ai, br, ci);
+        }
+        __syncthreads();                  // every wavefront is done with Ds and Ps
+        R* dst = P + (long long)j * mat;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = wr + (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+            const int c = wc + (lane & 15);
+            const int o = i * C32_LD + c;
+            const R nr = cr[v] + Ps[o];
+            const R ni = ci[v] + Ps[C32_PL + o];
+            Ps[o] = nr;
+            Ps[C32_PL + o] = ni;
+            dst[i * GT + c] = nr;
+            dst[plane + i * GT + c] = ni;
+        }
+        __syncthreads();                  // P_j complete in LDS before the next step
+    }
+}
+
+// Identity outside the leading 32 x 32 block of each of the K planar 64 x 64 matrices P_j.
+template <typename R>
+__global__ void k_gate_pad_identity(R* P, long long K) {
+    constexpr long long plane = (long long)GT * GT;
+    const long long total = K * 2 * plane;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long x = e % (2 * plane);
+        const int pl = (int)(x / plane), r = (int)((x % plane) / GT), c = (int)(x % GT);
+        if (r < 32 && c < 32) continue;
+        P[e] = (pl == 0 && r == c) ? R(1) : R(0);
+    }
+}
+
 // First propagator of every slice: P_{s_n} = I + D_{s_n} (blockIdx.y = n).
 template <typename R>
 __global__ void k_gate_first(const R* D, R* P, const int* s, int dp) {
