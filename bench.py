@@ -119,17 +119,18 @@ def _sparse_row_costs(prob):
     return h_rows, c_rows
 
 
-def algorithmic_flops(prob, m, S, B):
-    """Algorithmic FP operations per launch of the two hot kernels of the sparse path."""
+def algorithmic_flops(prob, terms):
+    """Algorithmic FP operations per launch of the two hot kernels of the sparse path;
+    terms[b] = generator applications per step of instance b (m_b S_b for the Taylor map,
+    n_b + 1 for Crank-Nicolson), as the library chose them."""
     h_rows, c_rows = _sparse_row_costs(prob)
     K, d, C = prob.K, prob.d, prob.C
-    vec_step = m * S * h_rows                       # one Taylor action on one vector
-    assemble = float(B) * K * d * vec_step          # d basis vectors through every step
-    per_step_slice = (3 * vec_step                  # forward, adjoint, reversal
-                      + C * vec_step                # H applied in each Frechet series
-                      + sum(m * S * cr for cr in c_rows)   # H_c applied to the adjoint terms
-                      + C * 8 * d)                  # overlaps
-    slice_ = float(B) * K * per_step_slice
+    B = len(terms)
+    mS = float(sum(terms))                          # sum over instances
+    assemble = K * d * h_rows * mS                  # d basis vectors through every step
+    slice_ = K * ((3 + C) * h_rows * mS             # forward, adjoint, reversal, Frechet
+                  + sum(cr for cr in c_rows) * mS   # H_c applied to the adjoint terms
+                  + B * C * 8 * d)                  # overlaps
     return {"sp_assemble": assemble, "sp_slice": slice_}
 
 
@@ -195,7 +196,7 @@ def _rotor_cn_workload(stream, steps=3):
     for prec, v in r.items():
         launches, ms = v["kernels"]["sp_assemble"]
         # (n + 1) applications of tau/2 H per step: (I - L) and n Neumann terms
-        fl = algorithmic_flops(prob, v["info"]["taylor_m"] + 1, 1, B)["sp_assemble"]
+        fl = algorithmic_flops(prob, [t + 1 for t in v["info"]["terms"]])["sp_assemble"]
         ach = fl / (ms / launches * 1e-3)
         ent[f"roofline_{prec}"] = {"bound": "alu", "kernel": "sp_assemble", "achieved": ach / 1e12,
                                    "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
@@ -228,7 +229,7 @@ def _rotor_inner_workload(stream, steps=3, ell=3):
            "final_F_mean": {k: v["F_mean"] for k, v in r.items()}}
     for prec, v in r.items():
         launches, ms = v["kernels"]["sp_slice"]
-        fl = algorithmic_flops(prob, v["info"]["taylor_m"], v["info"]["taylor_S"], B)["sp_slice"]
+        fl = algorithmic_flops(prob, v["info"]["terms"])["sp_slice"]
         ach = fl / (ms / launches * 1e-3)
         ent[f"roofline_slice_{prec}"] = {"bound": "alu", "kernel": "sp_slice", "achieved": ach / 1e12,
                                          "peak": PEAK_ALU / 1e12, "unit": "TFLOP/s",
@@ -351,6 +352,9 @@ def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp", 
     kt = h.kernel_times()
     h.set_timing(False)
     info = h.info()
+    if info["path"] == 0:
+        m_b, S_b = h.taylor_params()
+        info["terms"] = [m * S for m, S in zip(m_b, S_b)]
     J, F = h.fidelity()
     h.close()
     out = {"seconds": t1 - t0, "kernels": kt, "info": info, "J_mean": float(J.mean()),
@@ -424,7 +428,7 @@ def main():
     # roofline of the dominant kernel of the FP32 path (largest total time among the
     # kernels with an algorithmic flop count)
     kt = r32["kernels"]
-    flops = algorithmic_flops(prob, r32["info"]["taylor_m"], r32["info"]["taylor_S"], B)
+    flops = algorithmic_flops(prob, r32["info"]["terms"])
     dom = max((k for k in kt if k in flops), key=lambda k: kt[k][1])
     launches, tot_ms = kt[dom]
     achieved = flops.get(dom, 0.0) / (tot_ms / launches * 1e-3) if dom in flops else 0.0
@@ -454,7 +458,8 @@ def main():
                      "algorithmic_flop_per_launch": flops.get(dom)},
         "kernels": per_launch,
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
-        "taylor": {"m": r32["info"]["taylor_m"], "S": r32["info"]["taylor_S"]},
+        "taylor": {"m_max": r32["info"]["taylor_m"], "S_max": r32["info"]["taylor_S"],
+                   "terms_mean": sum(r32["info"]["terms"]) / len(r32["info"]["terms"])},
         "final_F_mean": r32["F_mean"],
     }
     if "fp64" in res:

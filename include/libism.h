@@ -232,6 +232,13 @@ typedef struct ism_info {
 } ism_info;
 int ism_problem_info(const ism_problem* p, ism_info* info);
 
+/* Sparse path: the series parameters of every instance at the last forward pass, Taylor
+ * terms m[b] and sub-steps S[b] per step (exponential map) or Neumann terms m[b] and S[b] = 1
+ * (Crank-Nicolson), b < batch; host arrays of batch ints, written after a synchronisation
+ * of the handle's stream.  ISM_E_STATE before the first forward pass, ISM_E_UNSUPPORTED on
+ * the dense and Gross-Pitaevskii paths. */
+int ism_taylor_params(const ism_problem* p, int* m, int* S);
+
 /*
  * Per-kernel timing (tracing).  With timing enabled, every kernel launch of the handle is
  * bracketed by two HIP events recorded on the handle's stream.  ism_kernel_times

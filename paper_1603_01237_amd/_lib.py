@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
 EXPORTED = [
     "ism_default_options", "ism_problem_create", "ism_problem_create_gpe", "ism_problem_destroy",
     "ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient",
-    "ism_iterate", "ism_iterate_inner", "ism_fidelity", "ism_problem_info", "ism_status_string", "ism_problem_footprint",
+    "ism_iterate", "ism_iterate_inner", "ism_fidelity", "ism_problem_info", "ism_taylor_params", "ism_status_string", "ism_problem_footprint",
     "ism_set_timing", "ism_kernel_times",
     "ism_server_clock", "ism_server_create", "ism_server_submit", "ism_server_progress",
     "ism_server_poll", "ism_server_take", "ism_server_stats_get", "ism_server_destroy",
@@ -117,6 +117,8 @@ def lib():
                                     vp, vp, ct.POINTER(ct.c_int)]
     L.ism_fidelity.argtypes = [vp, vp, vp]
     L.ism_problem_info.argtypes = [vp, ct.POINTER(Info)]
+    L.ism_taylor_params.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
+    L.ism_taylor_params.restype = ct.c_int
     L.ism_status_string.argtypes = [ct.c_int]
     L.ism_status_string.restype = ct.c_char_p
     L.ism_set_timing.argtypes = [vp, ct.c_int]
@@ -351,6 +353,13 @@ class Problem:
         n = ct.c_int(0)
         _check(lib().ism_kernel_times(self._h, arr, 32, ct.byref(n)), "ism_kernel_times")
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+    def taylor_params(self):
+        """Per-instance series terms m[b] and sub-steps S[b] of the sparse path."""
+        m = (ct.c_int * self.B)()
+        S = (ct.c_int * self.B)()
+        _check(lib().ism_taylor_params(self._h, m, S), "ism_taylor_params")
+        return list(m), list(S)
 
     def info(self) -> dict:
         i = Info()

@@ -739,6 +739,23 @@ int ism_problem_info(const ism_problem* p, ism_info* info) {
     return ISM_OK;
 }
 
+int ism_taylor_params(const ism_problem* p, int* m, int* S) {
+    if (!p || !m || !S) return ISM_E_ARG;
+    if (p->path != PATH_SPARSE) return ISM_E_UNSUPPORTED;
+    if (!p->tp || !p->tp_valid) return ISM_E_STATE;
+    std::vector<TaylorP> tp(p->B);
+    if (hipSetDevice(p->device) != hipSuccess ||
+        hipMemcpyAsync(tp.data(), p->tp, p->B * sizeof(TaylorP), hipMemcpyDeviceToHost,
+                       p->stream) != hipSuccess ||
+        hipStreamSynchronize(p->stream) != hipSuccess)
+        return ISM_E_DEVICE;
+    for (int b = 0; b < p->B; ++b) {
+        m[b] = tp[b].m;
+        S[b] = tp[b].S;
+    }
+    return ISM_OK;
+}
+
 int ism_set_timing(ism_problem* p, int enable) {
     if (!p) return ISM_E_ARG;
     p->timing = enable != 0;

@@ -102,6 +102,7 @@ def test_null_pointers_rejected():
     assert L.ism_gradient(None, None) == _lib.ISM_E_ARG
     assert L.ism_iterate(None, 1, 0.1, 2.0, None, None) == _lib.ISM_E_ARG
     assert L.ism_iterate_inner(None, 1, 2, 0.1, 2.0, 0.0, None, None, None) == _lib.ISM_E_ARG
+    assert L.ism_taylor_params(None, None, None) == _lib.ISM_E_ARG
     assert L.ism_fidelity(None, None, None) == _lib.ISM_E_ARG
     assert L.ism_set_controls(None, None) == _lib.ISM_E_ARG
     L.ism_problem_destroy(None)

@@ -227,3 +227,30 @@ def test_rotor_full_size_sampled():
     for prec, tol in (("fp32", 1e-4), ("fp64", tol64(p.K))):
         assert np.all(np.abs(np.linalg.norm(res[prec][1], axis=1) - 1) <= tol)
         assert np.all(np.isfinite(res[prec][0]))
+
+
+def test_taylor_params_per_instance():
+    """Per-instance series parameters: unavailable before a forward pass, one (m, S) per
+    instance after it, the largest equal to ism_problem_info's, and the FP32 truncation
+    budget (at most 1e-5 summed over the K steps) holding for every instance."""
+    import math
+    _say("case taylor params")
+    P = _P()
+    p = problems.rotor(batch=5, K=400, N=4, T=2.0)
+    with P.from_problem(p, precision="fp32") as h:
+        with pytest.raises(P.IsmError) as e:
+            h.taylor_params()
+        assert e.value.code == P.ISM_E_STATE
+        h.forward(want_state=False)
+        m, S = h.taylor_params()
+        info = h.info()
+    assert len(m) == 5 and max(m) == info["taylor_m"] and max(S) == info["taylor_S"]
+    tau = p.T / p.K
+    for b in range(5):
+        dg = np.real(np.diag(p.H0[b]))
+        bound = (np.abs(p.H0[b] - 0.5 * (dg.max() + dg.min()) * np.eye(p.d)).sum(1).max()
+                 + np.abs(p.u0[b]).max() * np.abs(p.Hc[0]).sum(1).max())
+        ts = tau * bound / S[b]
+        # first dropped term of the sub-step series, times e^ts: the truncation per step
+        drop = ts ** (m[b] + 1) / math.factorial(m[b] + 1) * math.exp(ts) * S[b]
+        assert drop * p.K <= 1e-5 * 1.0001
