@@ -218,6 +218,7 @@ static SpArgs sp_args(ism_problem* p, int assemble) {
     a.tau = p->tau;
     a.T = p->T;
     a.cn = p->step_cn;
+    a.mmax = p->tri ? kTriMaxTerms : 0;
     return a;
 }
 

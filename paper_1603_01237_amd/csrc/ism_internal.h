@@ -12,6 +12,9 @@
 namespace ism {
 
 struct dcx { double re, im; };   // interleaved complex, same layout as the ABI's double pairs
+
+// largest Taylor degree of the tridiagonal kernels, whose Horner series are unrolled
+constexpr int kTriMaxTerms = 12;
 struct fcx { float re, im; };
 
 enum Path { PATH_SPARSE = 0, PATH_GATE = 1, PATH_GPE = 2 };
@@ -49,6 +52,7 @@ struct SpArgs {
     double rho;
     int update;            // 1 => u += rho * g in place
     int cn;                // 1 => Crank-Nicolson step map (tp.m = Neumann terms, S = 1)
+    int mmax;              // largest Taylor degree the kernels accept (more sub-steps beyond)
     double tau, T;
 };
 

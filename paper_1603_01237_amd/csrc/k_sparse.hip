@@ -707,17 +707,23 @@ __global__ __launch_bounds__(256) void k_sp_params(SpArgs a, const double* h0nor
             tp.m = 1;
             atomicOr(&flags[0], 1);
         } else {
+            const int mcap = a.mmax > 0 ? a.mmax : MMAX;
             int S = (int)ceil(theta / cap);
             if (S < 1) S = 1;
-            const double ts = theta / S;
             int m = 1;
-            double term = ts;          // ts^{m} / m! for the current m
-            const double ex = exp(ts);
-            while (m < MMAX) {
-                const double next = term * ts / (m + 1);
-                if (next * ex * S <= tol) break;          // S sub-steps per step
-                term = next;
-                ++m;
+            for (;;) {                 // more sub-steps until the degree fits the kernels
+                const double ts = theta / S;
+                double term = ts;      // ts^{m} / m! for the current m
+                const double ex = exp(ts);
+                m = 1;
+                while (m < MMAX) {
+                    const double next = term * ts / (m + 1);
+                    if (next * ex * S <= tol) break;      // S sub-steps per step
+                    term = next;
+                    ++m;
+                }
+                if (m <= mcap) break;
+                ++S;
             }
             tp.S = S;
             tp.m = m;
@@ -1006,33 +1012,74 @@ __device__ __forceinline__ void tri_apply(const R (&xr)[RPL], const R (&xi)[RPL]
     }
 }
 
-// x <- e^{-i delta} T_m(-i (D + V)) x for one sub-step (Horner, as fwd_substep)
+// Horner terms up to this order are unrolled with 1/k as an instruction constant (terms
+// above the instance's m are skipped by a wavefront-uniform branch); larger m loop.
+constexpr int MU_TRI = kTriMaxTerms;
+
+// One Horner term: p <- x - i (D + V) p / k
 template <typename R>
-__device__ __forceinline__ void tri_fwd_substep(R (&nr)[RPL], R (&ni)[RPL], const R (&dg)[RPL],
-                                                const R (&dl)[RPL], const R (&Ls)[RPL],
-                                                const R (&Rs)[RPL], int left, int right, int m) {
-    R pr[RPL], pi[RPL];
+__device__ __forceinline__ void tri_fwd_term(R (&pr)[RPL], R (&pi)[RPL], const R (&nr)[RPL],
+                                             const R (&ni)[RPL], const R (&dg)[RPL],
+                                             const R (&Ls)[RPL], const R (&Rs)[RPL], int left,
+                                             int right, R rk) {
+    R lr, li, rr, ri, hr[RPL], hi[RPL];
+    tri_edges(pr, pi, left, right, lr, li, rr, ri);
+    tri_apply(pr, pi, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-        pr[q] = nr[q];
-        pi[q] = ni[q];
+        pr[q] = fma(hi[q], rk, nr[q]);
+        pi[q] = fma(-hr[q], rk, ni[q]);
     }
-#pragma unroll 1
-    for (int k = m; k >= 1; --k) {
+}
+
+// x <- T_M(-i (D + V)) x by Horner, M fixed: the first term is applied to x itself, so no
+// copy of x is made and every 1/k is an instruction constant.
+template <int M, typename R>
+__device__ __forceinline__ void tri_horner(R (&nr)[RPL], R (&ni)[RPL], const R (&dg)[RPL],
+                                           const R (&Ls)[RPL], const R (&Rs)[RPL], int left,
+                                           int right) {
+    R pr[RPL], pi[RPL];
+    {
         R lr, li, rr, ri, hr[RPL], hi[RPL];
-        tri_edges(pr, pi, left, right, lr, li, rr, ri);
-        tri_apply(pr, pi, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
-        const R rk = rk_of(R(0), k - 1);
+        tri_edges(nr, ni, left, right, lr, li, rr, ri);
+        tri_apply(nr, ni, lr, li, rr, ri, dg, Ls, Rs, hr, hi);
+        const R rk = R(1) / R(M);
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
-            pr[q] = fma(hi[q], rk, nr[q]);                // p <- x - i h / k
+            pr[q] = fma(hi[q], rk, nr[q]);
             pi[q] = fma(-hr[q], rk, ni[q]);
         }
     }
 #pragma unroll
+    for (int k = M - 1; k >= 1; --k) tri_fwd_term(pr, pi, nr, ni, dg, Ls, Rs, left, right, R(1) / R(k));
+#pragma unroll
     for (int q = 0; q < RPL; ++q) {
         nr[q] = pr[q];
         ni[q] = pi[q];
+    }
+}
+
+// the degree is wavefront-uniform: a chain of scalar branches selects the unrolled series
+template <int M, typename R>
+__device__ __forceinline__ void tri_horner_dispatch(int m, R (&nr)[RPL], R (&ni)[RPL],
+                                                    const R (&dg)[RPL], const R (&Ls)[RPL],
+                                                    const R (&Rs)[RPL], int left, int right) {
+    if (m == M) {
+        tri_horner<M>(nr, ni, dg, Ls, Rs, left, right);
+    } else {
+        if constexpr (M > 1) tri_horner_dispatch<M - 1>(m, nr, ni, dg, Ls, Rs, left, right);
+    }
+}
+
+// x <- e^{-i delta} T_m(-i (D + V)) x for one sub-step (Horner, as fwd_substep; m is at most
+// MU_TRI, which the series parameters guarantee for the tridiagonal kernels)
+template <typename R>
+__device__ __forceinline__ void tri_fwd_substep(R (&nr)[RPL], R (&ni)[RPL], const R (&dg)[RPL],
+                                                const R (&dl)[RPL], const R (&Ls)[RPL],
+                                                const R (&Rs)[RPL], int left, int right, int m) {
+    tri_horner_dispatch<MU_TRI>(m, nr, ni, dg, Ls, Rs, left, right);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
         if (sizeof(R) == 4) {                             // e^{-i delta}
             const R t = nr[q];
             nr[q] = fma(dl[q], ni[q], nr[q]);
@@ -1252,29 +1299,21 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
     const int left = (lane > 0 ? lane - 1 : 0) * 4, right = (lane < WAVE - 1 ? lane + 1 : lane) * 4;
     const double* ub = a.u + (size_t)b * a.K;       // one control
     double unext = ub[sn];
-    for (int jl = 0; jl < a.LMAX; ++jl) {
-        const bool act = valid && jl < L;
+    // each item runs its own slice length; the lanes of an item share it, so a lane whose
+    // item has finished only ever lends its (finite) state to an edge coupling that is zero
+    for (int jl = 0; jl < L; ++jl) {
         const R v = (R)unext;
         unext = ub[sn + (jl + 1 < L ? jl + 1 : L - 1)];
-        R Ls[RPL], Rs[RPL], nr[RPL], ni[RPL];
+        R Ls[RPL], Rs[RPL];
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
             Ls[q] = v * Lc[q];
             Rs[q] = v * Rc[q];
-            nr[q] = xr[q];
-            ni[q] = xi[q];
         }
         if (a.cn)
-            tri_fwd_cn(nr, ni, dg, dl, Ls, Rs, left, right, m);
+            tri_fwd_cn(xr, xi, dg, dl, Ls, Rs, left, right, m);
         else
-            for (int sub = 0; sub < S; ++sub) tri_fwd_substep(nr, ni, dg, dl, Ls, Rs, left, right, m);
-        if (act) {
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                xr[q] = nr[q];
-                xi[q] = ni[q];
-            }
-        }
+            for (int sub = 0; sub < S; ++sub) tri_fwd_substep(xr, xi, dg, dl, Ls, Rs, left, right, m);
     }
     if (valid) {
         R* M = reinterpret_cast<R*>(a.M);
