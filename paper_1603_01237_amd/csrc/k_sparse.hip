@@ -1192,52 +1192,58 @@ __device__ __forceinline__ void tri_adj_cn(R (&cr)[RPL], R (&ci)[RPL], R (&pr)[R
     }
 }
 
-// One sub-step of the block exponential of adj_substep in the tridiagonal layout:
-// (y, chi) <- exp([[A^+, E^+], [0, A^+]]) (y, chi) and psi <- exp(A^+) psi, with
-// A^+ = +i (D + v G), E^+ = +i G (G the unscaled control operator), then e^{+i delta} on
-// all three (FP32).
+// One Horner term of the adjoint block series: sources s* (the current terms, or the
+// sub-step's input for the first term) to outputs q*, around the input (c, p, y).
 template <typename R>
-__device__ __forceinline__ void tri_adj_substep(R (&cr)[RPL], R (&ci)[RPL], R (&pr)[RPL],
-                                                R (&pi)[RPL], R (&yr)[RPL], R (&yi)[RPL],
-                                                const R (&dg)[RPL], const R (&dl)[RPL],
-                                                const R (&Lc)[RPL], const R (&Rc)[RPL],
-                                                const R (&Ls)[RPL], const R (&Rs)[RPL], R v,
-                                                int left, int right, int m) {
-    R qcr[RPL], qci[RPL], qpr[RPL], qpi[RPL], qyr[RPL], qyi[RPL];
+__device__ __forceinline__ void tri_adj_term(const R (&scr)[RPL], const R (&sci)[RPL],
+                                             const R (&spr)[RPL], const R (&spi)[RPL],
+                                             const R (&syr)[RPL], const R (&syi)[RPL],
+                                             R (&qcr)[RPL], R (&qci)[RPL], R (&qpr)[RPL],
+                                             R (&qpi)[RPL], R (&qyr)[RPL], R (&qyi)[RPL],
+                                             const R (&cr)[RPL], const R (&ci)[RPL],
+                                             const R (&pr)[RPL], const R (&pi)[RPL],
+                                             const R (&yr)[RPL], const R (&yi)[RPL],
+                                             const R (&dg)[RPL], const R (&Lc)[RPL],
+                                             const R (&Rc)[RPL], const R (&Ls)[RPL],
+                                             const R (&Rs)[RPL], R v, int left, int right, R rk) {
     const R zero[RPL] = {};
+    R clr, cli, crr, cri, plr, pli, prr, pri, ylr, yli, yrr, yri;
+    tri_edges(scr, sci, left, right, clr, cli, crr, cri);
+    tri_edges(spr, spi, left, right, plr, pli, prr, pri);
+    tri_edges(syr, syi, left, right, ylr, yli, yrr, yri);
+    R gcr[RPL], gci[RPL], hpr[RPL], hpi[RPL], hyr[RPL], hyi[RPL];
+    tri_apply(scr, sci, clr, cli, crr, cri, zero, Lc, Rc, gcr, gci);   // G chi
+    tri_apply(spr, spi, plr, pli, prr, pri, dg, Ls, Rs, hpr, hpi);
+    tri_apply(syr, syi, ylr, yli, yrr, yri, dg, Ls, Rs, hyr, hyi);
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-        qcr[q] = cr[q];
-        qci[q] = ci[q];
-        qpr[q] = pr[q];
-        qpi[q] = pi[q];
-        qyr[q] = yr[q];
-        qyi[q] = yi[q];
+        const R hcr = fma(v, gcr[q], dg[q] * scr[q]), hci = fma(v, gci[q], dg[q] * sci[q]);
+        hyr[q] += gcr[q];                             // E^+ chi enters the y block
+        hyi[q] += gci[q];
+        qcr[q] = fma(-hci, rk, cr[q]);                // q <- x + i h / k
+        qci[q] = fma(hcr, rk, ci[q]);
+        qpr[q] = fma(-hpi[q], rk, pr[q]);
+        qpi[q] = fma(hpr[q], rk, pi[q]);
+        qyr[q] = fma(-hyi[q], rk, yr[q]);
+        qyi[q] = fma(hyr[q], rk, yi[q]);
     }
-#pragma unroll 1
-    for (int k = m; k >= 1; --k) {
-        R clr, cli, crr, cri, plr, pli, prr, pri, ylr, yli, yrr, yri;
-        tri_edges(qcr, qci, left, right, clr, cli, crr, cri);
-        tri_edges(qpr, qpi, left, right, plr, pli, prr, pri);
-        tri_edges(qyr, qyi, left, right, ylr, yli, yrr, yri);
-        R gcr[RPL], gci[RPL], hpr[RPL], hpi[RPL], hyr[RPL], hyi[RPL];
-        tri_apply(qcr, qci, clr, cli, crr, cri, zero, Lc, Rc, gcr, gci);   // G chi
-        tri_apply(qpr, qpi, plr, pli, prr, pri, dg, Ls, Rs, hpr, hpi);
-        tri_apply(qyr, qyi, ylr, yli, yrr, yri, dg, Ls, Rs, hyr, hyi);
-        const R rk = rk_of(R(0), k - 1);
+}
+
+// The adjoint block series of fixed degree M by Horner: the first term reads the input
+// itself, every 1/k is an instruction constant, and the result replaces the input.
+template <int M, typename R>
+__device__ __forceinline__ void tri_adj_horner(R (&cr)[RPL], R (&ci)[RPL], R (&pr)[RPL],
+                                               R (&pi)[RPL], R (&yr)[RPL], R (&yi)[RPL],
+                                               const R (&dg)[RPL], const R (&Lc)[RPL],
+                                               const R (&Rc)[RPL], const R (&Ls)[RPL],
+                                               const R (&Rs)[RPL], R v, int left, int right) {
+    R qcr[RPL], qci[RPL], qpr[RPL], qpi[RPL], qyr[RPL], qyi[RPL];
+    tri_adj_term(cr, ci, pr, pi, yr, yi, qcr, qci, qpr, qpi, qyr, qyi, cr, ci, pr, pi, yr, yi,
+                 dg, Lc, Rc, Ls, Rs, v, left, right, R(1) / R(M));
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const R hcr = fma(v, gcr[q], dg[q] * qcr[q]), hci = fma(v, gci[q], dg[q] * qci[q]);
-            hyr[q] += gcr[q];                             // E^+ chi enters the y block
-            hyi[q] += gci[q];
-            qcr[q] = fma(-hci, rk, cr[q]);                // q <- x + i h / k
-            qci[q] = fma(hcr, rk, ci[q]);
-            qpr[q] = fma(-hpi[q], rk, pr[q]);
-            qpi[q] = fma(hpr[q], rk, pi[q]);
-            qyr[q] = fma(-hyi[q], rk, yr[q]);
-            qyi[q] = fma(hyr[q], rk, yi[q]);
-        }
-    }
+    for (int k = M - 1; k >= 1; --k)
+        tri_adj_term(qcr, qci, qpr, qpi, qyr, qyi, qcr, qci, qpr, qpi, qyr, qyi, cr, ci, pr, pi,
+                     yr, yi, dg, Lc, Rc, Ls, Rs, v, left, right, R(1) / R(k));
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
         cr[q] = qcr[q];
@@ -1246,7 +1252,39 @@ __device__ __forceinline__ void tri_adj_substep(R (&cr)[RPL], R (&ci)[RPL], R (&
         pi[q] = qpi[q];
         yr[q] = qyr[q];
         yi[q] = qyi[q];
-        if (sizeof(R) == 4) {                             // e^{+i delta} on all three
+    }
+}
+
+template <int M, typename R>
+__device__ __forceinline__ void tri_adj_dispatch(int m, R (&cr)[RPL], R (&ci)[RPL],
+                                                 R (&pr)[RPL], R (&pi)[RPL], R (&yr)[RPL],
+                                                 R (&yi)[RPL], const R (&dg)[RPL],
+                                                 const R (&Lc)[RPL], const R (&Rc)[RPL],
+                                                 const R (&Ls)[RPL], const R (&Rs)[RPL], R v,
+                                                 int left, int right) {
+    if (m == M) {
+        tri_adj_horner<M>(cr, ci, pr, pi, yr, yi, dg, Lc, Rc, Ls, Rs, v, left, right);
+    } else {
+        if constexpr (M > 1)
+            tri_adj_dispatch<M - 1>(m, cr, ci, pr, pi, yr, yi, dg, Lc, Rc, Ls, Rs, v, left, right);
+    }
+}
+
+// One sub-step of the block exponential of adj_substep in the tridiagonal layout:
+// (y, chi) <- exp([[A^+, E^+], [0, A^+]]) (y, chi) and psi <- exp(A^+) psi, with
+// A^+ = +i (D + v G), E^+ = +i G (G the unscaled control operator), then e^{+i delta} on
+// all three (FP32).  m is at most MU_TRI.
+template <typename R>
+__device__ __forceinline__ void tri_adj_substep(R (&cr)[RPL], R (&ci)[RPL], R (&pr)[RPL],
+                                                R (&pi)[RPL], R (&yr)[RPL], R (&yi)[RPL],
+                                                const R (&dg)[RPL], const R (&dl)[RPL],
+                                                const R (&Lc)[RPL], const R (&Rc)[RPL],
+                                                const R (&Ls)[RPL], const R (&Rs)[RPL], R v,
+                                                int left, int right, int m) {
+    tri_adj_dispatch<MU_TRI>(m, cr, ci, pr, pi, yr, yi, dg, Lc, Rc, Ls, Rs, v, left, right);
+    if (sizeof(R) == 4) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {                   // e^{+i delta} on all three
             R t = cr[q];
             cr[q] = fma(-dl[q], ci[q], cr[q]);
             ci[q] = fma(dl[q], t, ci[q]);
