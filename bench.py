@@ -36,9 +36,9 @@ PEAK_ALU = 78.6e12       # non-packed FP32 and FP64 vector FMA rate: 256 CU x 64
 # change to them the field is reported as null until the counters are taken again.
 TRAFFIC_SOURCES = ["paper_1603_01237_amd/csrc/k_sparse.hip",
                    "paper_1603_01237_amd/csrc/ism_internal.h"]
-TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 32429.8, "write_kib": 113344.0,
+TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 32452.0, "write_kib": 113344.0,
            "copy_fetch_per_kib": 0.50001, "copy_write_per_kib": 1.0,
-           "sha256": "7c9969aa342842fefa000f797fdde22587a346158c472e895aa6cf15b674351c"}
+           "sha256": "786f890019e26f95870d5c12ea77d007701dcc0a03f8f41187a02a27c68180b7"}
 COPY_BYTES = 1 << 30
 
 
@@ -384,8 +384,8 @@ def cpu_baseline(prob, n_inst):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=3, help="oracle instances timed (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
