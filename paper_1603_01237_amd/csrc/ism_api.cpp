@@ -151,9 +151,11 @@ int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism
     std::vector<int> s(N + 1);
     for (int n = 0; n <= N; ++n) s[n] = (int)(((long long)n * K) / N);
     if ((st = dev_upload(p, (void**)&p->s, s.data(), s.size() * sizeof(int)))) return st;
-    std::vector<double> u0((size_t)p->B * K * C, 0.0);
+    // controls, plus zero padding: a kernel that prefetches the control of the step after a
+    // slice's last may read one element past the end
+    std::vector<double> u0((size_t)p->B * K * C + 8, 0.0);
     if ((st = dev_upload(p, (void**)&p->u, u0.data(), u0.size() * sizeof(double)))) return st;
-    if ((st = dev_alloc(p, (void**)&p->grad, u0.size() * sizeof(double)))) return st;
+    if ((st = dev_alloc(p, (void**)&p->grad, (u0.size() - 8) * sizeof(double)))) return st;
     if (o->alpha) {
         std::vector<double> al(K);
         for (int j = 0; j < K; ++j) al[j] = o->alpha_len == 1 ? o->alpha[0] : o->alpha[j];

@@ -1032,6 +1032,17 @@ __device__ __forceinline__ void tri_fwd_term(R (&pr)[RPL], R (&pi)[RPL], const R
     }
 }
 
+// x <- e^{-i k delta} x to first order (k delta ~ 1e-8)
+template <typename R>
+__device__ __forceinline__ void tri_phase(R (&nr)[RPL], R (&ni)[RPL], const R (&dl)[RPL], R k) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const R th = k * dl[q], t = nr[q];
+        nr[q] = fma(th, ni[q], nr[q]);
+        ni[q] = fma(-th, t, ni[q]);
+    }
+}
+
 // x <- T_M(-i (D + V)) x by Horner, M fixed: the first term is applied to x itself, so no
 // copy of x is made and every 1/k is an instruction constant.
 template <int M, typename R>
@@ -1073,14 +1084,14 @@ __device__ __forceinline__ void tri_horner_dispatch(int m, R (&nr)[RPL], R (&ni)
 
 // x <- e^{-i delta} T_m(-i (D + V)) x for one sub-step (Horner, as fwd_substep; m is at most
 // MU_TRI, which the series parameters guarantee for the tridiagonal kernels)
-template <typename R>
+template <typename R, bool PHASE = true>
 __device__ __forceinline__ void tri_fwd_substep(R (&nr)[RPL], R (&ni)[RPL], const R (&dg)[RPL],
                                                 const R (&dl)[RPL], const R (&Ls)[RPL],
                                                 const R (&Rs)[RPL], int left, int right, int m) {
     tri_horner_dispatch<MU_TRI>(m, nr, ni, dg, Ls, Rs, left, right);
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-        if (sizeof(R) == 4) {                             // e^{-i delta}
+        if (PHASE && sizeof(R) == 4) {                    // e^{-i delta}
             const R t = nr[q];
             nr[q] = fma(dl[q], ni[q], nr[q]);
             ni[q] = fma(-dl[q], t, ni[q]);
@@ -1335,24 +1346,40 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
     }
     const int sn = a.s[n], L = a.s[n + 1] - sn;
     const int left = (lane > 0 ? lane - 1 : 0) * 4, right = (lane < WAVE - 1 ? lane + 1 : lane) * 4;
-    const double* ub = a.u + (size_t)b * a.K;       // one control
-    double unext = ub[sn];
+    // this item's controls (one control); the element after the slice's last is readable
+    // (the next slice's first, or the allocation's padding)
+    const double* up = a.u + (size_t)b * a.K + sn;
+    double unext = up[0];
+    // FP32: the residual phase e^{-i delta} of each sub-step is applied as e^{-i k delta}
+    // once k >= 4 sub-steps have accumulated (delta ~ 1e-8: deferring it past the coupling
+    // part changes a step by ~1e-12)
+    int pend = 0;
     // each item runs its own slice length; the lanes of an item share it, so a lane whose
     // item has finished only ever lends its (finite) state to an edge coupling that is zero
     for (int jl = 0; jl < L; ++jl) {
         const R v = (R)unext;
-        unext = ub[sn + (jl + 1 < L ? jl + 1 : L - 1)];
+        unext = up[jl + 1];
         R Ls[RPL], Rs[RPL];
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
             Ls[q] = v * Lc[q];
             Rs[q] = v * Rc[q];
         }
-        if (a.cn)
+        if (a.cn) {
             tri_fwd_cn(xr, xi, dg, dl, Ls, Rs, left, right, m);
-        else
-            for (int sub = 0; sub < S; ++sub) tri_fwd_substep(xr, xi, dg, dl, Ls, Rs, left, right, m);
+        } else {
+            for (int sub = 0; sub < S; ++sub)
+                tri_fwd_substep<R, false>(xr, xi, dg, dl, Ls, Rs, left, right, m);
+            if (sizeof(R) == 4) {
+                pend += S;
+                if (pend >= 4) {
+                    tri_phase(xr, xi, dl, (R)pend);
+                    pend = 0;
+                }
+            }
+        }
     }
+    if (sizeof(R) == 4 && pend > 0) tri_phase(xr, xi, dl, (R)pend);
     if (valid) {
         R* M = reinterpret_cast<R*>(a.M);
         const size_t o = (((size_t)b * a.N + n) * d + col) * d;
