@@ -57,6 +57,7 @@ CASES = [
     ("spin5_K437_N5_ragged", lambda: problems.spin5_density(K=437, N=5, u_amp=300.0)),
     ("spin5_K512_N16", lambda: problems.spin5_density(K=512, N=16, u_amp=300.0)),
     ("random_d4_K30_N3_alpha", lambda: _random_density(4, 30, 3, 7, alpha=0.2)),
+    ("random_d4_K1_N1_single_step", lambda: _random_density(4, 1, 1, 9, T=0.05)),
     ("chain7_d128_K12_N3", lambda: _chain_density(7, 12, 3)),
 ]
 

@@ -35,8 +35,8 @@ def _gate_problem(n, K, N, seed=5, T=None):
     return p
 
 
-def _spin2_gate(K, N, seed=3):
-    p = problems.spin2(K=K, N=N)
+def _spin2_gate(K, N, seed=3, T=1.0):
+    p = problems.spin2(K=K, N=N, T=T)
     rng = np.random.default_rng(seed)
     W = problems.haar_unitary(4, rng)
     u = rng.uniform(-1, 1, size=(1, K, 2))
@@ -47,6 +47,7 @@ def _spin2_gate(K, N, seed=3):
 CASES = [
     ("spin2_gate_K24_N3", lambda: _spin2_gate(24, 3)),
     ("spin2_gate_K17_N5", lambda: _spin2_gate(17, 5)),
+    ("spin2_gate_K1_N1_single_step", lambda: _spin2_gate(1, 1, T=0.1)),
     ("chain4_gate_K30_N4", lambda: _gate_problem(4, 30, 4)),
     ("chain6_gate_K13_N13", lambda: _gate_problem(6, 13, 13)),
 ]

@@ -53,6 +53,7 @@ CASES = [
     ("n4096_K30_N1", lambda: _small(n=4096, K=30, N=1)),
     ("n1024_g0_K25_N5", lambda: _small(K=25, N=5, g=0.0)),
     ("n1024_batch2", lambda: _small(K=20, N=3, batch=2)),
+    ("n1024_K1_N1_single_step", lambda: _small(K=1, N=1, T=0.01)),
 ]
 
 

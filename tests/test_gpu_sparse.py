@@ -47,6 +47,8 @@ CASES = [
     ("spin2_K37_N5_ragged", lambda: problems.spin2(K=37, N=5)),
     ("spin2_K16_N16_NeqK", lambda: problems.spin2(K=16, N=16)),
     ("spin2_K25_N1", lambda: problems.spin2(K=25, N=1)),
+    ("spin2_K1_N1_single_step", lambda: problems.spin2(K=1, N=1)),
+    ("rotor_B2_K1_N1_single_step", lambda: problems.rotor(batch=2, K=1, N=1, T=0.01)),
     ("rotor_B3_K90_N7", lambda: problems.rotor(batch=3, K=90, N=7, T=0.5)),
     ("rotor_j40_B2_K40_N6", lambda: problems.rotor(batch=2, jmax=40, K=40, N=6, T=0.1)),
     # three-rows-per-lane layout: padded last lane (d=11), 32 items per wavefront (d=5),
