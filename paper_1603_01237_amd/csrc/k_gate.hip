@@ -507,6 +507,22 @@ __global__ void k_gate_pad_identity(R* P, long long K) {
     }
 }
 
+// First step of every slice (blockIdx.y = n): [X | Y]^+ at step s_n is RHS_n^+ (RHS_n is
+// dp x 2dp planar, the output 2dp x dp planar).
+template <typename R>
+__global__ void k_gate_rhs_adj(const R* RHS, R* XY, const int* s, int dp) {
+    const long long rplane = 2LL * dp * dp;
+    const R* src = RHS + (long long)blockIdx.y * 2 * rplane;
+    R* dst = XY + (long long)s[blockIdx.y] * 2 * rplane;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < rplane;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / dp), c = (int)(e % dp);     // output row i < 2dp, column c < dp
+        const long long o = (long long)c * 2 * dp + i;       // RHS_n[c][i]
+        dst[e] = src[o];
+        dst[e + rplane] = -src[o + rplane];
+    }
+}
+
 // First propagator of every slice: P_{s_n} = I + D_{s_n} (blockIdx.y = n).
 template <typename R>
 __global__ void k_gate_first(const R* D, R* P, const int* s, int dp) {
@@ -545,7 +561,7 @@ __device__ constexpr WabTable kWab = make_wab();
 // 2 tau ||H_j - s||_inf above 1.46 in FP64 or 2.0 in FP32.
 template <typename R, int MK, int WT>
 __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
-                                                   int ldxy, double* gpart, int ncb, int* flags) {
+                                                   double* gpart, int ncb, int* flags) {
     // LDS: per-row gradient accumulators of every control; Krylov vectors (tau H')^b x,
     // b = 0..MK, as re/im planes; a double buffer for the Krylov vectors of y; the
     // per-wavefront partial sums of the final reduction.
@@ -598,9 +614,11 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
         const int k = cb * CBW + kk;
         if (k >= d) break;                    // uniform over the workgroup
         // column k of X_j (x) and Y_j (y)
-        const long long ox = (long long)j * xy_plane * 2 + (long long)r * ldxy + k;
-        R xr = r < d ? XY[ox] : R(0), xi = r < d ? XY[ox + xy_plane] : R(0);
-        R yr = r < d ? XY[ox + dp] : R(0), yi = r < d ? XY[ox + dp + xy_plane] : R(0);
+        // stored as [X_j | Y_j]^+: column k of X_j is row k, conjugated; of Y_j row dp + k
+        const long long ox = (long long)j * xy_plane * 2 + (long long)k * dp + r;
+        const long long oy = ox + (long long)dp * dp;
+        R xr = r < d ? XY[ox] : R(0), xi = r < d ? -XY[ox + xy_plane] : R(0);
+        R yr = r < d ? XY[oy] : R(0), yi = r < d ? -XY[oy + xy_plane] : R(0);
         __syncthreads();                      // the previous column's readers of kv are done
         kv[r] = xr;
         kv[dp + r] = xi;
