@@ -209,7 +209,7 @@ __device__ __forceinline__ int taylor_terms(double theta, double tol, int& S) {
 template <typename R, int WT>
 __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long plane, int* flags) {
     __shared__ dcx vs[RB][256];
-    const int j = blockIdx.x, r0 = blockIdx.y * RB, c = threadIdx.x;
+    const int j = blockIdx.x, c = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
     const double* uj = gg.u + (size_t)j * gg.C;
     // row c of conj(H_j - s) on the union pattern
@@ -219,7 +219,10 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
     for (int q = 0; q < gg.C; ++q) theta += fabs(uj[q]) * gg.cnorm[q];
     theta *= gg.tau;
     int S;
-    int m = taylor_terms(theta, 1e-17, S);
+    // FP64 path: truncation below FP64 rounding.  FP32 path (U_j stored in FP32): the
+    // truncation summed over the K steps below 1e-5, never above 1e-8 per step
+    const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
+    int m = taylor_terms(theta, tol, S);
     if (m < 0) {
         if (c == 0 && blockIdx.y == 0) atomicOr(flags, 1);
         m = 1;
@@ -243,59 +246,64 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
         hv[w].im = -ts * h.im;
         hc[w] = cc;
     }
-    dcx acc[RB], tr[RB];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-        acc[q].re = (c == r0 + q) ? 1.0 : 0.0;
-        acc[q].im = 0.0;
-    }
-    for (int sub = 0; sub < S; ++sub) {
-#pragma unroll
-        for (int q = 0; q < RB; ++q) tr[q] = acc[q];
-        for (int k = 0; k < m; ++k) {
-#pragma unroll
-            for (int q = 0; q < RB; ++q) vs[q][c] = tr[q];
-            __syncthreads();
-            const double rk = 1.0 / (k + 1);
-#pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                double ar = 0.0, ai = 0.0;
-#pragma unroll
-                for (int w = 0; w < WT; ++w) {
-                    const dcx x = vs[q][hc[w]];
-                    ar = fma(hv[w].re, x.re, fma(-hv[w].im, x.im, ar));
-                    ai = fma(hv[w].re, x.im, fma(hv[w].im, x.re, ai));
-                }
-                tr[q].re = ai * rk;      // -i (h x) / (k+1)
-                tr[q].im = -ar * rk;
-                acc[q].re += tr[q].re;
-                acc[q].im += tr[q].im;
-            }
-            __syncthreads();
-        }
-    }
-    const double ph = -gg.tau * gg.shift;
-    const double cp = cos(ph), sp = sin(ph);
-    if (c < dp) {
+    // the generator row above is set up once and serves every row block of this workgroup
+    const int nrb = (d + RB - 1) / RB;
+    for (int rb = blockIdx.y; rb < nrb; rb += gridDim.y) {
+        const int r0 = rb * RB;
+        dcx acc[RB], tr[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            const int r = r0 + q;
-            if (r >= dp) break;
-            const long long o = (long long)j * plane * 2 + (long long)r * dp + c;
-            double xr = acc[q].re, xi = acc[q].im;
-            if (r >= d || c >= d) {            // padded block: identity
-                xr = (r == c) ? 1.0 : 0.0;
-                xi = 0.0;
-            } else {
-                const double yr = cp * xr - sp * xi, yi = cp * xi + sp * xr;
-                xr = yr;
-                xi = yi;
+            acc[q].re = (c == r0 + q) ? 1.0 : 0.0;
+            acc[q].im = 0.0;
+        }
+        for (int sub = 0; sub < S; ++sub) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) tr[q] = acc[q];
+            for (int k = 0; k < m; ++k) {
+#pragma unroll
+                for (int q = 0; q < RB; ++q) vs[q][c] = tr[q];
+                __syncthreads();
+                const double rk = 1.0 / (k + 1);
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    double ar = 0.0, ai = 0.0;
+#pragma unroll
+                    for (int w = 0; w < WT; ++w) {
+                        const dcx x = vs[q][hc[w]];
+                        ar = fma(hv[w].re, x.re, fma(-hv[w].im, x.im, ar));
+                        ai = fma(hv[w].re, x.im, fma(hv[w].im, x.re, ai));
+                    }
+                    tr[q].re = ai * rk;      // -i (h x) / (k+1)
+                    tr[q].im = -ar * rk;
+                    acc[q].re += tr[q].re;
+                    acc[q].im += tr[q].im;
+                }
+                __syncthreads();
             }
-            // stored as D_j = U_j - I: at small tau U_j is close to I, and rounding I + delta
-            // to FP32 would make the same error at every step of a slice
-            if (r == c) xr -= 1.0;
-            U[o] = (R)xr;
-            U[o + plane] = (R)xi;
+        }
+        const double ph = -gg.tau * gg.shift;
+        const double cp = cos(ph), sp = sin(ph);
+        if (c < dp) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int r = r0 + q;
+                if (r >= dp) break;
+                const long long o = (long long)j * plane * 2 + (long long)r * dp + c;
+                double xr = acc[q].re, xi = acc[q].im;
+                if (r >= d || c >= d) {            // padded block: identity
+                    xr = (r == c) ? 1.0 : 0.0;
+                    xi = 0.0;
+                } else {
+                    const double yr = cp * xr - sp * xi, yi = cp * xi + sp * xr;
+                    xr = yr;
+                    xi = yi;
+                }
+                // stored as D_j = U_j - I: at small tau U_j is close to I, and rounding I + delta
+                // to FP32 would make the same error at every step of a slice
+                if (r == c) xr -= 1.0;
+                U[o] = (R)xr;
+                U[o + plane] = (R)xi;
+            }
         }
     }
 }
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
     int m = 1;
     {
         const double x = 2.0 * gg.tau * bound;
-        const double tol = sizeof(R) == 8 ? 1e-17 : 1e-10;
+        const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
         double t = x * x / 6.0;
         while (m < MK && t > tol) {
             ++m;
