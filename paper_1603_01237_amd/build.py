@@ -35,14 +35,31 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _dynamic_stack_kernels(remarks: str) -> list:
+    """Kernels whose resource report says their stack is sized at run time.  Scratch is
+    allocated from the static size, so such a kernel can run past its scratch (an
+    out-of-bounds access on the GPU); the build refuses them."""
+    bad, name = [], None
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:", 1)[1].split("[")[0].strip()
+        elif "Dynamic Stack: True" in line and name:
+            bad.append(name)
+    return bad
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [_hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    bad = _dynamic_stack_kernels(r.stderr)
+    if bad:
+        raise RuntimeError(f"{src}: kernels with a dynamically sized stack: {bad}")
     return obj
 
 

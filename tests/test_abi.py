@@ -151,3 +151,15 @@ def test_request_problems_of_trace_are_well_formed():
     arr = np.array([r["arrival"] for r in problems.serving_trace()])
     assert np.all(np.diff(arr) > 0)
     assert abs(len(arr) / arr[-1] - 200.0) < 20.0     # 2000 arrivals at a mean rate of 200/s
+
+
+def test_build_refuses_kernels_with_a_dynamic_stack():
+    """The build parses the compiler's resource report and refuses a kernel whose stack is
+    sized at run time (its scratch would be allocated from the static size only)."""
+    from paper_1603_01237_amd import build
+    ok = ("k.hip:1:1: remark: Function Name: _Z3fooPf [-Rpass-analysis=kernel-resource-usage]\n"
+          "k.hip:1:1: remark:     Dynamic Stack: False [-Rpass-analysis=kernel-resource-usage]\n")
+    bad = ok + ("k.hip:9:1: remark: Function Name: _Z3barPd [-Rpass-analysis=kernel-resource-usage]\n"
+                "k.hip:9:1: remark:     Dynamic Stack: True [-Rpass-analysis=kernel-resource-usage]\n")
+    assert build._dynamic_stack_kernels(ok) == []
+    assert build._dynamic_stack_kernels(bad) == ["_Z3barPd"]
