@@ -5,14 +5,15 @@
 //   build     U_j = exp(-i tau H_j) for every step, in FP64 (row r of U_j is the
 //             action of exp(-i tau conj(H_j)) on e_r, a truncated Taylor series of a
 //             sparse generator), stored in the path's precision, re/im planes split;
-//   assemble  P_j = U_j U_{j-1} ... U_{s_n} for every step of slice n (chain of batched
-//             complex GEMMs over the slices); M_n = P_{s_{n+1}-1}  (propagator
-//             assembling, Sec. 3);
+//   assemble  P_j = U_j U_{j-1} ... U_{s_n} for every step of slice n (d <= 64: a chunked
+//             scan of 32 x 32 or 64 x 64 products; larger d: a chain of batched complex
+//             GEMMs over the slices); M_n = P_{s_{n+1}-1}  (propagator assembling, Sec. 3);
 //   boundary  Psi_{n+1} = M_n Psi_n, Lambda_n = M_n^+ Lambda_{n+1} (FP64 GEMMs),
 //             phi_n (Eq. (cible)), J and F;
 //   sweeps    the slice trajectories from phi_n (forward) and phi_{n+1} (adjoint) are
 //             X_j = P_{j-1} phi_n and Y_j = P_{j-1} (M_n^+ phi_{n+1}), one batched GEMM
-//             [X_j | Y_j] = P_{j-1} [phi_n | M_n^+ phi_{n+1}] over every step at once;
+//             [X_j | Y_j] = P_{j-1} [phi_n | M_n^+ phi_{n+1}] over every step at once
+//             (d <= 32: on the leading 32 x 32 blocks only);
 //   gradient  g_{j,c} = beta_n Im Tr(Y_j^+ Hhat_{c,j} X_j)/d - alpha_j u_{j,c} (Theorem 2),
 //             with the step average Hhat of H_c evaluated column by column through
 //               <y|Hhat_c|x> = sum_{a+b<=m} w_ab <(tau H')^a y | H_c | (tau H')^b x>,
@@ -27,6 +28,8 @@
 // Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.  FP32 operands with FP32 accumulation
 // (mixed path) or FP64 throughout (plain path; the boundary products are FP64 in both).
 #include <math.h>
+
+#include <cmath>
 
 #include <algorithm>
 #include <vector>
@@ -308,199 +311,6 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
     }
 }
 
-// Assembly chain of one slice in one workgroup, for dp = 64 (blockIdx.x = n):
-// P_{s_n} = I + D_{s_n}, then P_j = P_{j-1} + D_j P_{j-1} for the rest of the slice.
-// P_{j-1} stays in LDS between steps and D_{j+1} is fetched into registers while step j
-// runs on MFMA, so a slice costs one pass over its D_j and no launch per step.  LDS:
-// Ds[p][k][i] = D_j[i][k] and Ps[p][k][c] = P_{j-1}[k][c], p = re/im, rows padded to 65.
-constexpr int CH_LD = GT + 1;
-constexpr int CH_PL = GT * CH_LD;
-
-template <typename R>
-static size_t gate_chain_shmem() {
-    return (size_t)4 * CH_PL * sizeof(R);
-}
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_gate_chain64(const R* D, R* P, const int* s) {
-    extern __shared__ unsigned char smem_raw[];
-    R* Ds = reinterpret_cast<R*>(smem_raw);
-    R* Ps = Ds + 2 * CH_PL;
-    constexpr long long plane = (long long)GT * GT, mat = 2 * plane;
-    constexpr int PER = (int)(mat / 256);            // matrix entries per thread
-    const int n = blockIdx.x;
-    const int j0 = s[n], j1 = s[n + 1];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    R pre[PER];
-    // entry e = t + 256 q of a planar matrix: plane e / 4096, row (e % 4096) / 64, column e % 64
-    {
-        const R* src = D + (long long)j0 * mat;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) pre[q] = src[t + 256 * q];
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int e = t + 256 * q, p = e >> 12, r = (e >> 6) & 63, c = e & 63;
-        const R v = pre[q] + ((p == 0 && r == c) ? R(1) : R(0));
-        Ps[p * CH_PL + r * CH_LD + c] = v;
-        P[(long long)j0 * mat + e] = v;
-    }
-    if (j0 + 1 < j1) {
-        const R* src = D + (long long)(j0 + 1) * mat;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) pre[q] = src[t + 256 * q];
-    }
-    __syncthreads();
-    for (int j = j0 + 1; j < j1; ++j) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + 256 * q, p = e >> 12, r = (e >> 6) & 63, c = e & 63;
-            Ds[p * CH_PL + c * CH_LD + r] = pre[q];
-        }
-        __syncthreads();
-        if (j + 1 < j1) {
-            const R* src = D + (long long)(j + 1) * mat;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) pre[q] = src[t + 256 * q];
-        }
-        typename Acc<R>::T cr[2][2], ci[2][2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0;
-#pragma unroll 4
-        for (int kk = 0; kk < GT; kk += 4) {
-            const int kr = kk + (lane >> 4), li = lane & 15;
-            R ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                ar[a] = Ds[kr * CH_LD + wr + a * 16 + li];
-                ai[a] = Ds[CH_PL + kr * CH_LD + wr + a * 16 + li];
-            }
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                br[b] = Ps[kr * CH_LD + wc + b * 16 + li];
-                bi[b] = Ps[CH_PL + kr * CH_LD + wc + b * 16 + li];
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    cr[a][b] = mfma16(ar[a], br[b], cr[a][b]);
-                    cr[a][b] = mfma16(-ai[a], bi[b], cr[a][b]);
-                    ci[a][b] = mfma16(ar[a], bi[b], ci[a][b]);
-                    ci[a][b] = mfma16(ai[a], br[b], ci[a][b]);
-                }
-        }
-        __syncthreads();                  // every wavefront is done with Ds and Ps
-        R* dst = P + (long long)j * mat;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = wr + a * 16 +
-                                  (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
-                    const int c = wc + b * 16 + (lane & 15);
-                    const int o = i * CH_LD + c;
-                    const R nr = cr[a][b][v] + Ps[o];
-                    const R ni = ci[a][b][v] + Ps[CH_PL + o];
-                    Ps[o] = nr;
-                    Ps[CH_PL + o] = ni;
-                    dst[i * GT + c] = nr;
-                    dst[plane + i * GT + c] = ni;
-                }
-        __syncthreads();                  // P_j complete in LDS before the next step
-    }
-}
-
-// The same chain for d <= 32: only the leading 32 x 32 block of every P_j is formed (one
-// 16 x 16 MFMA block per wavefront, a quarter of the columns of the 64 x 64 tile and an
-// eighth of its work); the rest of each P_j is the identity, written once by
-// k_gate_pad_identity, and the rest of each D_j is zero.
-constexpr int C32_LD = 33;
-constexpr int C32_PL = 32 * C32_LD;
-
-template <typename R>
-__global__ __launch_bounds__(256) void k_gate_chain32(const R* D, R* P, const int* s) {
-    __shared__ R Ds[2 * C32_PL];   // Ds[p][k][i] = D_j[i][k]
-    __shared__ R Ps[2 * C32_PL];   // Ps[p][k][c] = P_{j-1}[k][c]
-    constexpr long long plane = (long long)GT * GT, mat = 2 * plane;
-    constexpr int PER = 2 * 32 * 32 / 256;
-    const int n = blockIdx.x;
-    const int j0 = s[n], j1 = s[n + 1];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
-    R pre[PER];
-    // entry e = t + 256 q of the leading block: plane e / 1024, row (e % 1024) / 32, column e % 32
-    auto gidx = [](int e) -> long long {
-        return (long long)(e >> 10) * plane + ((e >> 5) & 31) * GT + (e & 31);
-    };
-    {
-        const R* src = D + (long long)j0 * mat;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) pre[q] = src[gidx(t + 256 * q)];
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int e = t + 256 * q, p = e >> 10, r = (e >> 5) & 31, c = e & 31;
-        const R v = pre[q] + ((p == 0 && r == c) ? R(1) : R(0));
-        Ps[p * C32_PL + r * C32_LD + c] = v;
-        P[(long long)j0 * mat + gidx(e)] = v;
-    }
-    if (j0 + 1 < j1) {
-        const R* src = D + (long long)(j0 + 1) * mat;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) pre[q] = src[gidx(t + 256 * q)];
-    }
-    __syncthreads();
-    for (int j = j0 + 1; j < j1; ++j) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = t + 256 * q, p = e >> 10, r = (e >> 5) & 31, c = e & 31;
-            Ds[p * C32_PL + c * C32_LD + r] = pre[q];
-        }
-        __syncthreads();
-        if (j + 1 < j1) {
-            const R* src = D + (long long)(j + 1) * mat;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) pre[q] = src[gidx(t + 256 * q)];
-        }
-        typename Acc<R>::T cr, ci;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cr[v] = ci[v] = 0;
-#pragma unroll
-        for (int kk = 0; kk < 32; kk += 4) {
-            const int kr = kk + (lane >> 4), li = lane & 15;
-            const R ar = Ds[kr * C32_LD + wr + li], ai = Ds[C32_PL + kr * C32_LD + wr + li];
-            const R br = Ps[kr * C32_LD + wc + li], bi = Ps[C32_PL + kr * C32_LD + wc + li];
-            cr = mfma16(ar, br, cr);
-            cr = mfma16(-ai, bi, cr);
-            ci = mfma16(ar, bi, ci);
-            ci = mfma16(ai, br, ci);
-        }
-        __syncthreads();                  // every wavefront is done with Ds and Ps
-        R* dst = P + (long long)j * mat;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = wr + (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
-            const int c = wc + (lane & 15);
-            const int o = i * C32_LD + c;
-            const R nr = cr[v] + Ps[o];
-            const R ni = ci[v] + Ps[C32_PL + o];
-            Ps[o] = nr;
-            Ps[C32_PL + o] = ni;
-            dst[i * GT + c] = nr;
-            dst[plane + i * GT + c] = ni;
-        }
-        __syncthreads();                  // P_j complete in LDS before the next step
-    }
-}
-
 // Identity outside the leading 32 x 32 block of each of the K planar 64 x 64 matrices P_j.
 template <typename R>
 __global__ void k_gate_pad_identity(R* P, long long K) {
@@ -512,6 +322,326 @@ __global__ void k_gate_pad_identity(R* P, long long K) {
         const int pl = (int)(x / plane), r = (int)((x % plane) / GT), c = (int)(x % GT);
         if (r < 32 && c < 32) continue;
         P[e] = (pl == 0 && r == c) ? R(1) : R(0);
+    }
+}
+
+// Chunked assembly scan (d <= 64).  The prefix products of a slice form a scan over its
+// steps; run as one chain it keeps one workgroup busy per slice.  The steps are cut into
+// chunks of consecutive steps inside the slices, and
+//  1. k_gate_chain runs every chunk from the identity (one workgroup per chunk), giving
+//     the local prefixes Q_j = U_j ... U_{first step of the chunk};
+//  2. k_gate_carry (one workgroup per slice) turns the last local prefix of each chunk into
+//     the true prefix, chunk after chunk: P_e(c) = Q_e(c) P_e(c-1) (e(c) the last step of
+//     chunk c; the first chunk of a slice already holds true prefixes);
+//  3. k_gate_apply (one workgroup per chunk after the first of a slice) multiplies the
+//     other local prefixes by the true prefix that ends the previous chunk:
+//     P_j = Q_j P_e(c-1).
+// The dependent chain shrinks from the slice length L to about 2 Lc + L / Lc products.
+// Local prefixes are kept as E_j = Q_j - I (a chunk's Q_j stays close to I, and rounding
+// I + small to the path's precision at every step would lose the small part); steps 2 and 3
+// form P = B + E B, each rounding like one addition.
+// BS is the block formed: the leading 32 x 32 block (d <= 32, the rest of each P_j is the
+// identity) or the whole 64 x 64 matrix.  Blocks live in LDS as A^T (left factor) and
+// row-major (right factor), rows padded to BS + 1.
+template <int BS>
+__device__ __forceinline__ long long blk_gidx(int e) {
+    constexpr long long plane = (long long)GT * GT;
+    return (long long)(e / (BS * BS)) * plane + ((e / BS) % BS) * GT + (e % BS);
+}
+
+template <typename R, int BS>
+static size_t gate_scan_shmem() {
+    return (size_t)4 * BS * (BS + 1) * sizeof(R);
+}
+
+// C = A B for the two BS x BS blocks in LDS (At[p][k][i] = A[i][k], Bs[p][k][c] = B[k][c]);
+// each wavefront owns a (BS/2) x (BS/2) quarter of C as (BS/32)^2 16 x 16 MFMA tiles.
+template <typename R, int BS>
+__device__ __forceinline__ void blk_mm(const R* At, const R* Bs, typename Acc<R>::T (&cr)[BS / 32][BS / 32],
+                                       typename Acc<R>::T (&ci)[BS / 32][BS / 32]) {
+    constexpr int LD = BS + 1, PL = BS * LD, NT = BS / 32;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * (BS / 2), wc = (w & 1) * (BS / 2);
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0;
+#pragma unroll 4
+    for (int kk = 0; kk < BS; kk += 4) {
+        const int kr = kk + (lane >> 4), li = lane & 15;
+        R ar[NT], ai[NT], br[NT], bi[NT];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) {
+            ar[a] = At[kr * LD + wr + a * 16 + li];
+            ai[a] = At[PL + kr * LD + wr + a * 16 + li];
+        }
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            br[b] = Bs[kr * LD + wc + b * 16 + li];
+            bi[b] = Bs[PL + kr * LD + wc + b * 16 + li];
+        }
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                cr[a][b] = mfma16(ar[a], br[b], cr[a][b]);
+                cr[a][b] = mfma16(-ai[a], bi[b], cr[a][b]);
+                ci[a][b] = mfma16(ar[a], bi[b], ci[a][b]);
+                ci[a][b] = mfma16(ai[a], br[b], ci[a][b]);
+            }
+    }
+}
+
+// Row and column of accumulator element v of tile (a, b) of this lane's wavefront.
+template <typename R, int BS>
+__device__ __forceinline__ void blk_rc(int a, int b, int v, int& i, int& c) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    i = (w >> 1) * (BS / 2) + a * 16 + (sizeof(R) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+    c = (w & 1) * (BS / 2) + b * 16 + (lane & 15);
+}
+
+// Step 1 of the scan, blockIdx.x = chunk c (steps cb[c] .. cb[c+1]-1):
+// E_first = D_first, E_j = E_{j-1} + (D_j + D_j E_{j-1}) with D_j = U_j - I.  The sum is
+// compensated (Kahan) by the lane that owns the entry: the increments of neighbouring steps
+// are alike, so their roundings would otherwise add up instead of cancelling.  E_{j-1} stays
+// in LDS and D_{j+1} is fetched while step j runs on MFMA.  The first chunk of a slice
+// stores I + E_j (true prefixes), the others E_j.
+template <typename R, int BS>
+__global__ __launch_bounds__(256) void k_gate_chain(const R* D, R* P, const int* cb, const int* s, int N) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int LD = BS + 1, PL = BS * LD, NT = BS / 32, PER = 2 * BS * BS / 256;
+    constexpr long long mat = 2LL * GT * GT;
+    R* Dt = reinterpret_cast<R*>(smem_raw);   // Dt[p][k][i] = D_j[i][k]
+    R* Es = Dt + 2 * PL;                       // Es[p][k][c] = E_{j-1}[k][c]
+    const int ch = blockIdx.x, j0 = cb[ch], j1 = cb[ch + 1], t = threadIdx.x;
+    int lo = 0, hi = N;                        // the chunk is the first of its slice when
+    while (hi - lo > 1) {                      // it starts at a slice start
+        const int mid = (lo + hi) >> 1;
+        if (s[mid] <= j0) lo = mid; else hi = mid;
+    }
+    const R one = s[lo] == j0 ? R(1) : R(0);
+    R pre[PER];
+    {
+        const R* src = D + (long long)j0 * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[blk_gidx<BS>(t + 256 * q)];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+        Es[p * PL + r * LD + c] = pre[q];
+        P[(long long)j0 * mat + blk_gidx<BS>(e)] = pre[q] + ((p == 0 && r == c) ? one : R(0));
+    }
+    if (j0 + 1 < j1) {
+        const R* src = D + (long long)(j0 + 1) * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = src[blk_gidx<BS>(t + 256 * q)];
+    }
+    R kr[NT][NT][4], ki[NT][NT][4];           // compensation of the owned entries
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+        for (int b = 0; b < NT; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) kr[a][b][v] = ki[a][b][v] = 0;
+    __syncthreads();
+    for (int j = j0 + 1; j < j1; ++j) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            Dt[p * PL + c * LD + r] = pre[q];
+        }
+        __syncthreads();                  // D_j complete in LDS
+        if (j + 1 < j1) {
+            const R* src = D + (long long)(j + 1) * mat;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) pre[q] = src[blk_gidx<BS>(t + 256 * q)];
+        }
+        typename Acc<R>::T cr[NT][NT], ci[NT][NT];
+        blk_mm<R, BS>(Dt, Es, cr, ci);
+        __syncthreads();                  // every wavefront is done with Es
+        R* dst = P + (long long)j * mat;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i, c;
+                    blk_rc<R, BS>(a, b, v, i, c);
+                    const int o = i * LD + c;
+                    const R yr = (cr[a][b][v] + Dt[c * LD + i]) - kr[a][b][v];
+                    const R yi = (ci[a][b][v] + Dt[PL + c * LD + i]) - ki[a][b][v];
+                    const R er = Es[o], ei = Es[PL + o];
+                    const R tr = er + yr, ti = ei + yi;
+                    kr[a][b][v] = (tr - er) - yr;
+                    ki[a][b][v] = (ti - ei) - yi;
+                    Es[o] = tr;
+                    Es[PL + o] = ti;
+                    dst[i * GT + c] = tr + (i == c ? one : R(0));
+                    dst[GT * GT + i * GT + c] = ti;
+                }
+        __syncthreads();                  // E_j complete in LDS, Dt free for the next step
+    }
+}
+
+// Step 2 of the scan, blockIdx.x = slice n: chunks cfirst[n] .. cfirst[n+1]-1 with step
+// bounds cb (chunk c covers steps cb[c] .. cb[c+1]-1); P_e(c) = P_e(c-1) + E_e(c) P_e(c-1).
+template <typename R, int BS>
+__global__ __launch_bounds__(256) void k_gate_carry(R* P, const int* cb, const int* cfirst) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int LD = BS + 1, PL = BS * LD, NT = BS / 32, PER = 2 * BS * BS / 256;
+    constexpr long long mat = 2LL * GT * GT;
+    R* At = reinterpret_cast<R*>(smem_raw);
+    R* Bs = At + 2 * PL;
+    const int n = blockIdx.x, c0 = cfirst[n], c1 = cfirst[n + 1];
+    if (c1 - c0 < 2) return;
+    const int t = threadIdx.x;
+    R pre[PER];
+    {
+        const R* src = P + (long long)(cb[c0 + 1] - 1) * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            Bs[p * PL + r * LD + c] = src[blk_gidx<BS>(e)];
+        }
+        const R* nxt = P + (long long)(cb[c0 + 2] - 1) * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = nxt[blk_gidx<BS>(t + 256 * q)];
+    }
+    for (int ch = c0 + 1; ch < c1; ++ch) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            At[p * PL + c * LD + r] = pre[q];
+        }
+        __syncthreads();                  // A and B complete in LDS
+        if (ch + 1 < c1) {
+            const R* nxt = P + (long long)(cb[ch + 2] - 1) * mat;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) pre[q] = nxt[blk_gidx<BS>(t + 256 * q)];
+        }
+        typename Acc<R>::T cr[NT][NT], ci[NT][NT];
+        blk_mm<R, BS>(At, Bs, cr, ci);
+        __syncthreads();                  // every wavefront is done with At and Bs
+        R* dst = P + (long long)(cb[ch + 1] - 1) * mat;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i, c;
+                    blk_rc<R, BS>(a, b, v, i, c);
+                    const R nr = cr[a][b][v] + Bs[i * LD + c];
+                    const R ni = ci[a][b][v] + Bs[PL + i * LD + c];
+                    Bs[i * LD + c] = nr;
+                    Bs[PL + i * LD + c] = ni;
+                    dst[i * GT + c] = nr;
+                    dst[GT * GT + i * GT + c] = ni;
+                }
+    }
+}
+
+// Step 3 of the scan, blockIdx.x = entry of capply: a chunk c that is not the first of its
+// slice.  Its last product was made true by step 2; the others become
+// P_{cb[c]-1} + E_j P_{cb[c]-1}.
+template <typename R, int BS>
+__global__ __launch_bounds__(256) void k_gate_apply(R* P, const int* cb, const int* capply) {
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int LD = BS + 1, PL = BS * LD, NT = BS / 32, PER = 2 * BS * BS / 256;
+    constexpr long long mat = 2LL * GT * GT;
+    R* At = reinterpret_cast<R*>(smem_raw);
+    R* Bs = At + 2 * PL;
+    const int ch = capply[blockIdx.x];
+    const int j0 = cb[ch], j1 = cb[ch + 1] - 1;
+    if (j0 >= j1) return;
+    const int t = threadIdx.x;
+    R pre[PER];
+    {
+        const R* src = P + (long long)(j0 - 1) * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            Bs[p * PL + r * LD + c] = src[blk_gidx<BS>(e)];
+        }
+        const R* nxt = P + (long long)j0 * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = nxt[blk_gidx<BS>(t + 256 * q)];
+    }
+    for (int j = j0; j < j1; ++j) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            At[p * PL + c * LD + r] = pre[q];
+        }
+        __syncthreads();                  // Q_j complete in LDS
+        if (j + 1 < j1) {
+            const R* nxt = P + (long long)(j + 1) * mat;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) pre[q] = nxt[blk_gidx<BS>(t + 256 * q)];
+        }
+        typename Acc<R>::T cr[NT][NT], ci[NT][NT];
+        blk_mm<R, BS>(At, Bs, cr, ci);
+        R* dst = P + (long long)j * mat;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i, c;
+                    blk_rc<R, BS>(a, b, v, i, c);
+                    dst[i * GT + c] = cr[a][b][v] + Bs[i * LD + c];
+                    dst[GT * GT + i * GT + c] = ci[a][b][v] + Bs[PL + i * LD + c];
+                }
+        __syncthreads();                  // every wavefront is done with At
+    }
+}
+
+// Slice products for d <= 32, blockIdx.x = step j: [X_j | Y_j] = P_{j-1} [phi_n | B_n] on
+// the leading 32 x 32 blocks only (P_{j-1}, phi_n and B_n are block diagonal in the padded
+// layout and the gradient reads no other entry), written as [X_j | Y_j]^+ (2dp x dp planar,
+// dp = 64).  The first step of a slice is left to k_gate_rhs_adj.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gate_xy32(const R* RHS, const R* P, R* XY, const int* s, int N) {
+    constexpr int BS = 32, LD = BS + 1, PL = BS * LD, PER = 2 * BS * BS / 256;
+    constexpr long long plane = (long long)GT * GT, mat = 2 * plane;
+    constexpr long long rplane = 2 * plane, rmat = 2 * rplane;   // dp x 2dp and 2dp x dp
+    __shared__ R At[2 * PL], Bx[2 * PL], By[2 * PL];
+    const int j = blockIdx.x, t = threadIdx.x;
+    int lo = 0, hi = N;                   // slice n: s[n] <= j < s[n+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s[mid] <= j) lo = mid; else hi = mid;
+    }
+    const int n = lo;
+    if (j == s[n]) return;
+    const R* Pm = P + (long long)(j - 1) * mat;
+    const R* Rn = RHS + (long long)n * rmat;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+        At[p * PL + c * LD + r] = Pm[p * plane + r * GT + c];
+        Bx[p * PL + r * LD + c] = Rn[p * rplane + r * 2 * GT + c];
+        By[p * PL + r * LD + c] = Rn[p * rplane + r * 2 * GT + GT + c];
+    }
+    __syncthreads();
+    typename Acc<R>::T xr[1][1], xi[1][1], yr[1][1], yi[1][1];
+    blk_mm<R, BS>(At, Bx, xr, xi);
+    blk_mm<R, BS>(At, By, yr, yi);
+    R* out = XY + (long long)j * rmat;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int i, c;
+        blk_rc<R, BS>(0, 0, v, i, c);
+        // row c of X^+ holds conj(X[i][c]) at column i; Y^+ starts at row dp
+        out[(long long)c * GT + i] = xr[0][0][v];
+        out[rplane + (long long)c * GT + i] = -xi[0][0][v];
+        out[(long long)(GT + c) * GT + i] = yr[0][0][v];
+        out[rplane + (long long)(GT + c) * GT + i] = -yi[0][0][v];
     }
 }
 
@@ -564,6 +694,10 @@ __device__ constexpr WabTable kWab = make_wab();
 
 // Per (step, block of CBW columns): partial sums over rows and columns of
 // Im <y_k| Hhat_c |x_k> for every control c, in FP64.  MK bounds the Krylov order.
+// Thread t works on row r = t mod lpc of column group t / lpc: lpc = dp (one column at a
+// time) unless d <= 32, where lpc is the least power of two >= d and a workgroup of dp = 64
+// threads takes 64 / lpc columns at once (rows d..dp-1 of the padded layout are never
+// worked on).  Slot t of every LDS vector belongs to thread t.
 // A step whose series, cut at MK terms, leaves a remainder bound above 1e-13 (FP64) or 1e-7
 // (FP32) sets bit 1 of flags[0] (reported as unsupported, never truncated silently):
 // 2 tau ||H_j - s||_inf above 1.46 in FP64 or 2.0 in FP32.
@@ -578,8 +712,14 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
     R* kv = reinterpret_cast<R*>(gacc + (size_t)gg.C * gg.dp);  // 2 (MK+1) dp
     R* yb = kv + 2 * (MK + 1) * gg.dp;                          // 2 x 2 dp
     __shared__ double red[4][CMAX_G];
-    const int j = blockIdx.x, cb = blockIdx.y, r = threadIdx.x;
+    const int j = blockIdx.x, cb = blockIdx.y, t = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
+    int lpc = dp;
+    if (d <= 32) {
+        lpc = 1;
+        while (lpc < d) lpc <<= 1;
+    }
+    const int r = t & (lpc - 1), base = t - r, grp = t / lpc, ngrp = dp / lpc;
     const double* uj = gg.u + (size_t)j * gg.C;
     double bound = gg.h0norm;
     for (int q = 0; q < gg.C; ++q) bound += fabs(uj[q]) * gg.cnorm[q];
@@ -588,12 +728,12 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
     {
         const double x = 2.0 * gg.tau * bound;
         const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
-        double t = x * x / 6.0;
-        while (m < MK && t > tol) {
+        double rem = x * x / 6.0;
+        while (m < MK && rem > tol) {
             ++m;
-            t = t * x / (m + 2);
+            rem = rem * x / (m + 2);
         }
-        if (t > (sizeof(R) == 8 ? 1e-13 : 1e-7) && r == 0 && cb == 0) atomicOr(flags, 2);
+        if (rem > (sizeof(R) == 8 ? 1e-13 : 1e-7) && t == 0 && cb == 0) atomicOr(flags, 2);
     }
     // row r of tau (H_j - s) on the union pattern
     R hvr[WT], hvi[WT];
@@ -617,21 +757,22 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
         hvi[w] = (R)(gg.tau * hi);
         hcol[w] = cc;
     }
-    for (int q = 0; q < gg.C; ++q) gacc[q * dp + r] = 0.0;     // own slots only
-    for (int kk = 0; kk < CBW; ++kk) {
-        const int k = cb * CBW + kk;
-        if (k >= d) break;                    // uniform over the workgroup
-        // column k of X_j (x) and Y_j (y)
+    for (int q = 0; q < gg.C; ++q) gacc[q * dp + t] = 0.0;     // own slots only
+    for (int kk = 0; kk < CBW; kk += ngrp) {
+        if (cb * CBW + kk >= d) break;        // uniform over the workgroup
+        // column k of X_j (x) and Y_j (y) for this thread's group
         // stored as [X_j | Y_j]^+: column k of X_j is row k, conjugated; of Y_j row dp + k
+        const int k = cb * CBW + kk + grp;
+        const bool live = r < d && k < d && kk + grp < CBW;
         const long long ox = (long long)j * xy_plane * 2 + (long long)k * dp + r;
         const long long oy = ox + (long long)dp * dp;
-        R xr = r < d ? XY[ox] : R(0), xi = r < d ? -XY[ox + xy_plane] : R(0);
-        R yr = r < d ? XY[oy] : R(0), yi = r < d ? -XY[oy + xy_plane] : R(0);
+        R xr = live ? XY[ox] : R(0), xi = live ? -XY[ox + xy_plane] : R(0);
+        R yr = live ? XY[oy] : R(0), yi = live ? -XY[oy + xy_plane] : R(0);
         __syncthreads();                      // the previous column's readers of kv are done
-        kv[r] = xr;
-        kv[dp + r] = xi;
-        yb[r] = yr;
-        yb[dp + r] = yi;
+        kv[t] = xr;
+        kv[dp + t] = xi;
+        yb[t] = yr;
+        yb[dp + t] = yi;
         // t_b = sum_a conj(w_ab) p_a, p_a = (tau H')^a y, with
         // conj(w_ab) = (-i)^{a+b} (-1)^b |w_ab|, accumulated as the p_a are produced
         R ttr[MK + 1], tti[MK + 1];
@@ -642,8 +783,8 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
             if (a > 0) {
                 // Krylov step a of x and y (every thread reaches the barrier every time)
                 __syncthreads();
-                const R* xs = kv + 2 * (a - 1) * dp;
-                const R* ys = yb + 2 * ((a - 1) & 1) * dp;
+                const R* xs = kv + 2 * (a - 1) * dp + base;
+                const R* ys = yb + 2 * ((a - 1) & 1) * dp + base;
                 R nxr = 0, nxi = 0, nyr = 0, nyi = 0;
                 if (a <= m) {
 #pragma unroll
@@ -655,10 +796,10 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
                         nyr = fma(hvr[w], vr, fma(-hvi[w], vi, nyr));
                         nyi = fma(hvr[w], vi, fma(hvi[w], vr, nyi));
                     }
-                    kv[2 * a * dp + r] = nxr;
-                    kv[(2 * a + 1) * dp + r] = nxi;
-                    yb[2 * (a & 1) * dp + r] = nyr;
-                    yb[(2 * (a & 1) + 1) * dp + r] = nyi;
+                    kv[2 * a * dp + t] = nxr;
+                    kv[(2 * a + 1) * dp + t] = nxi;
+                    yb[2 * (a & 1) * dp + t] = nyr;
+                    yb[(2 * (a & 1) + 1) * dp + t] = nyi;
                 }
                 yr = nyr;
                 yi = nyi;
@@ -680,7 +821,7 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
         }
         __syncthreads();                      // all Krylov vectors of x are in kv
         // per control: Im of sum_b conj(t_b) (H_c r_b)_row
-        if (r < d) {
+        if (live) {
             for (int q = 0; q < gg.C; ++q) {
                 double sacc = 0.0;
                 for (int wc = 0; wc < gg.WCc; ++wc) {
@@ -693,29 +834,29 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
 #pragma unroll
                     for (int b = 0; b <= MK; ++b) {
                         if (b <= m) {
-                            const R rr = kv[(2 * b) * dp + cc], ri = kv[(2 * b + 1) * dp + cc];
+                            const R rr = kv[(2 * b) * dp + base + cc], ri = kv[(2 * b + 1) * dp + base + cc];
                             sr = fma(ttr[b], rr, fma(tti[b], ri, sr));
                             si = fma(ttr[b], ri, fma(-tti[b], rr, si));
                         }
                     }
                     sacc += hv.re * (double)si + hv.im * (double)sr;
                 }
-                gacc[q * dp + r] += sacc;
+                gacc[q * dp + t] += sacc;
             }
         }
     }
     // reduction over rows: wavefront tree, then the four partials in order
-    const int wv = r >> 6, lane = r & 63;
+    const int wv = t >> 6, lane = t & 63;
     for (int q = 0; q < gg.C; ++q) {
-        double v = r < d ? gacc[q * dp + r] : 0.0;
+        double v = gacc[q * dp + t];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) red[wv][q] = v;
     }
     __syncthreads();
-    if (r < gg.C) {
+    if (t < gg.C) {
         double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][r];
-        gpart[((size_t)j * ncb + cb) * gg.C + r] = s;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][t];
+        gpart[((size_t)j * ncb + cb) * gg.C + t] = s;
     }
 }
 // g_{j,c} = beta_n (1/d) sum_cb gpart - alpha_j u_{j,c}; update or write the gradient.

@@ -50,6 +50,9 @@ CASES = [
     ("spin2_gate_K1_N1_single_step", lambda: _spin2_gate(1, 1, T=0.1)),
     ("chain4_gate_K30_N4", lambda: _gate_problem(4, 30, 4)),
     ("chain6_gate_K13_N13", lambda: _gate_problem(6, 13, 13)),
+    # slices long enough for the chunked assembly scan (local chains, carries, fix-up)
+    ("chain6_gate_K300_N3_scan64", lambda: _gate_problem(6, 300, 3)),
+    ("spin2_gate_K400_N1_scan32", lambda: _spin2_gate(400, 1, T=4.0)),
 ]
 
 
