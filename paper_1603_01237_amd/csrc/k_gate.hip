@@ -209,11 +209,21 @@ __device__ __forceinline__ int taylor_terms(double theta, double tol, int& S) {
 }
 
 // Rows r0..r0+RB-1 of U_j = e^{-i tau s} exp(-i tau (H_j - s)) (FP64), stored as R.
+// Thread t holds component c = t mod lpc of the rows of row block t / lpc: lpc = dp unless
+// d <= 32, where lpc is the least power of two >= d and a workgroup of dp = 64 threads takes
+// 64 / lpc row blocks at once.  Entries of D_j outside the problem's rows and columns are
+// zero from the clear at create and are not written.
 template <typename R, int WT>
 __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long plane, int* flags) {
     __shared__ dcx vs[RB][256];
-    const int j = blockIdx.x, c = threadIdx.x;
+    const int j = blockIdx.x, t = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
+    int lpc = dp;
+    if (d <= 32) {
+        lpc = 1;
+        while (lpc < d) lpc <<= 1;
+    }
+    const int c = t & (lpc - 1), base = t - c, grp = t / lpc, ngrp = dp / lpc;
     const double* uj = gg.u + (size_t)j * gg.C;
     // row c of conj(H_j - s) on the union pattern
     dcx hv[WT];
@@ -227,7 +237,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
     const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
     int m = taylor_terms(theta, tol, S);
     if (m < 0) {
-        if (c == 0 && blockIdx.y == 0) atomicOr(flags, 1);
+        if (t == 0 && blockIdx.y == 0) atomicOr(flags, 1);
         m = 1;
     }
     const double ts = gg.tau / S;
@@ -251,7 +261,8 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
     }
     // the generator row above is set up once and serves every row block of this workgroup
     const int nrb = (d + RB - 1) / RB;
-    for (int rb = blockIdx.y; rb < nrb; rb += gridDim.y) {
+    for (int rbb = blockIdx.y * ngrp; rbb < nrb; rbb += gridDim.y * ngrp) {   // uniform
+        const int rb = rbb + grp;
         const int r0 = rb * RB;
         dcx acc[RB], tr[RB];
 #pragma unroll
@@ -264,7 +275,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
             for (int q = 0; q < RB; ++q) tr[q] = acc[q];
             for (int k = 0; k < m; ++k) {
 #pragma unroll
-                for (int q = 0; q < RB; ++q) vs[q][c] = tr[q];
+                for (int q = 0; q < RB; ++q) vs[q][t] = tr[q];
                 __syncthreads();
                 const double rk = 1.0 / (k + 1);
 #pragma unroll
@@ -272,7 +283,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
                     double ar = 0.0, ai = 0.0;
 #pragma unroll
                     for (int w = 0; w < WT; ++w) {
-                        const dcx x = vs[q][hc[w]];
+                        const dcx x = vs[q][base + hc[w]];
                         ar = fma(hv[w].re, x.re, fma(-hv[w].im, x.im, ar));
                         ai = fma(hv[w].re, x.im, fma(hv[w].im, x.re, ai));
                     }
@@ -286,7 +297,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
         }
         const double ph = -gg.tau * gg.shift;
         const double cp = cos(ph), sp = sin(ph);
-        if (c < dp) {
+        if (rb < nrb) {
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 const int r = r0 + q;
