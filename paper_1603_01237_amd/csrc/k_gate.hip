@@ -208,13 +208,34 @@ __device__ __forceinline__ int taylor_terms(double theta, double tol, int& S) {
     return m;
 }
 
-// Rows r0..r0+RB-1 of U_j = e^{-i tau s} exp(-i tau (H_j - s)) (FP64), stored as R.
+// Krylov order of the gradient series at step j (at most cap): the dropped terms
+// (2 theta)^n / (n+1)!, n > m, theta = tau (||H_0 - s|| + sum_c |u_c| ||H_c||), are below
+// the path's tolerance; rem is the first dropped term.
+template <typename R>
+__device__ __forceinline__ int grad_order(const GateGen& gg, int j, int cap, double& rem) {
+    const double* uj = gg.u + (size_t)j * gg.C;
+    double bound = gg.h0norm;
+    for (int q = 0; q < gg.C; ++q) bound += fabs(uj[q]) * gg.cnorm[q];
+    const double x = 2.0 * gg.tau * bound;
+    const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
+    int m = 1;
+    rem = x * x / 6.0;
+    while (m < cap && rem > tol) {
+        ++m;
+        rem = rem * x / (m + 2);
+    }
+    return m;
+}
+
+// Rows r0..r0+RB-1 of U_j = e^{-i tau s} exp(-i tau (H_j - s)) (FP64), stored as R; the
+// largest Krylov order the gradient needs at these controls goes to kmax (cleared before).
 // Thread t holds component c = t mod lpc of the rows of row block t / lpc: lpc = dp unless
 // d <= 32, where lpc is the least power of two >= d and a workgroup of dp = 64 threads takes
 // 64 / lpc row blocks at once.  Entries of D_j outside the problem's rows and columns are
 // zero from the clear at create and are not written.
 template <typename R, int WT>
-__global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long plane, int* flags) {
+__global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long plane, int* flags,
+                                                    int* kmax) {
     __shared__ dcx vs[RB][256];
     const int j = blockIdx.x, t = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
@@ -320,7 +341,15 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
             }
         }
     }
+    if (t == 0 && blockIdx.y == 0) {      // the gradient's Krylov order at this step
+        double rem;
+        const int mj = grad_order<R>(gg, j, MMAX_G + 1, rem);
+        // most steps need the same order: update only when it is above the value seen so far
+        if (mj > __hip_atomic_load(kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(kmax, mj);
+    }
 }
+
+__global__ void k_gate_set_int(int* v, int x) { *v = x; }
 
 // Identity outside the leading 32 x 32 block of each of the K planar 64 x 64 matrices P_j.
 template <typename R>
@@ -712,9 +741,15 @@ __device__ constexpr WabTable kWab = make_wab();
 // A step whose series, cut at MK terms, leaves a remainder bound above 1e-13 (FP64) or 1e-7
 // (FP32) sets bit 1 of flags[0] (reported as unsupported, never truncated silently):
 // 2 tau ||H_j - s||_inf above 1.46 in FP64 or 2.0 in FP32.
+// Two bounds MK are launched: the one with MK = mks runs when every step's order is at
+// most mks (kmax, from the step build at the same controls; then the order of every step is
+// the same as with the larger bound, and so is the result), the other one otherwise.  The
+// smaller bound holds fewer registers and more wavefronts per SIMD.
 template <typename R, int MK, int WT>
 __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
-                                                   double* gpart, int ncb, int* flags) {
+                                                   double* gpart, int ncb, int* flags,
+                                                   const int* kmax, int mks) {
+    if ((*kmax <= mks) != (MK == mks)) return;      // the other bound's launch does this work
     // LDS: per-row gradient accumulators of every control; Krylov vectors (tau H')^b x,
     // b = 0..MK, as re/im planes; a double buffer for the Krylov vectors of y; the
     // per-wavefront partial sums of the final reduction.
@@ -732,18 +767,10 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
     }
     const int r = t & (lpc - 1), base = t - r, grp = t / lpc, ngrp = dp / lpc;
     const double* uj = gg.u + (size_t)j * gg.C;
-    double bound = gg.h0norm;
-    for (int q = 0; q < gg.C; ++q) bound += fabs(uj[q]) * gg.cnorm[q];
-    // order m: the dropped terms (2 theta)^n / (n+1)!, n > m, are below the tolerance
-    int m = 1;
+    int m;
     {
-        const double x = 2.0 * gg.tau * bound;
-        const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
-        double rem = x * x / 6.0;
-        while (m < MK && rem > tol) {
-            ++m;
-            rem = rem * x / (m + 2);
-        }
+        double rem;
+        m = grad_order<R>(gg, j, MK, rem);
         if (rem > (sizeof(R) == 8 ? 1e-13 : 1e-7) && t == 0 && cb == 0) atomicOr(flags, 2);
     }
     // row r of tau (H_j - s) on the union pattern
