@@ -923,11 +923,14 @@ __global__ void k_gate_grad_finish(const double* gpart, int ncb, int K, int N, i
     if (update) u[idx] = fma(rho, g, uu);
 }
 
+// Slice propagators M_n = P_{s_{n+1}-1} to FP64, blockIdx.y = n.
 template <typename R>
-__global__ void k_to_f64(const R* src, double* dst, long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_slice_ends_f64(const R* P, double* M64, const int* s, long long mat) {
+    const R* src = P + (long long)(s[blockIdx.y + 1] - 1) * mat;
+    double* dst = M64 + (long long)blockIdx.y * mat;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) dst[i] = (double)src[i];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < mat; i += stride)
+        dst[i] = (double)src[i];
 }
 
 template <typename R>

@@ -53,6 +53,9 @@ CASES = [
     # slices long enough for the chunked assembly scan (local chains, carries, fix-up)
     ("chain6_gate_K300_N3_scan64", lambda: _gate_problem(6, 300, 3)),
     ("spin2_gate_K400_N1_scan32", lambda: _spin2_gate(400, 1, T=4.0)),
+    # 16 or more slices: the FP64 boundaries run as a chunked scan (ragged chunks at N = 19)
+    ("chain4_gate_K57_N19_bscan", lambda: _gate_problem(4, 57, 19)),
+    ("spin2_gate_K40_N20_bscan", lambda: _spin2_gate(40, 20, T=2.0)),
 ]
 
 
