@@ -53,6 +53,16 @@ template <typename R> struct Acc;
 template <> struct Acc<float> { typedef f4 T; };
 template <> struct Acc<double> { typedef d4 T; };
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also orders global memory, so it
+// waits for every global load in flight (a prefetch issued before it is then no prefetch);
+// this one waits for the LDS operations alone.  For loops whose threads exchange data
+// through LDS only, with every prefetched value consumed before the next barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -486,14 +496,14 @@ __global__ __launch_bounds__(256) void k_gate_chain(const R* D, R* P, const int*
         for (int b = 0; b < NT; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) kr[a][b][v] = ki[a][b][v] = 0;
-    __syncthreads();
+    lds_barrier();
     for (int j = j0 + 1; j < j1; ++j) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
             Dt[p * PL + c * LD + r] = pre[q];
         }
-        __syncthreads();                  // D_j complete in LDS
+        lds_barrier();                  // D_j complete in LDS
         if (j + 1 < j1) {
             const R* src = D + (long long)(j + 1) * mat;
 #pragma unroll
@@ -501,7 +511,7 @@ __global__ __launch_bounds__(256) void k_gate_chain(const R* D, R* P, const int*
         }
         typename Acc<R>::T cr[NT][NT], ci[NT][NT];
         blk_mm<R, BS>(Dt, Es, cr, ci);
-        __syncthreads();                  // every wavefront is done with Es
+        lds_barrier();                  // every wavefront is done with Es
         R* dst = P + (long long)j * mat;
 #pragma unroll
         for (int a = 0; a < NT; ++a)
@@ -523,7 +533,7 @@ __global__ __launch_bounds__(256) void k_gate_chain(const R* D, R* P, const int*
                     dst[i * GT + c] = tr + (i == c ? one : R(0));
                     dst[GT * GT + i * GT + c] = ti;
                 }
-        __syncthreads();                  // E_j complete in LDS, Dt free for the next step
+        lds_barrier();                  // E_j complete in LDS, Dt free for the next step
     }
 }
 
@@ -557,7 +567,7 @@ __global__ __launch_bounds__(256) void k_gate_carry(R* P, const int* cb, const i
             const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
             At[p * PL + c * LD + r] = pre[q];
         }
-        __syncthreads();                  // A and B complete in LDS
+        lds_barrier();                  // A and B complete in LDS
         if (ch + 1 < c1) {
             const R* nxt = P + (long long)(cb[ch + 2] - 1) * mat;
 #pragma unroll
@@ -565,7 +575,7 @@ __global__ __launch_bounds__(256) void k_gate_carry(R* P, const int* cb, const i
         }
         typename Acc<R>::T cr[NT][NT], ci[NT][NT];
         blk_mm<R, BS>(At, Bs, cr, ci);
-        __syncthreads();                  // every wavefront is done with At and Bs
+        lds_barrier();                  // every wavefront is done with At and Bs
         R* dst = P + (long long)(cb[ch + 1] - 1) * mat;
 #pragma unroll
         for (int a = 0; a < NT; ++a)
@@ -617,7 +627,7 @@ __global__ __launch_bounds__(256) void k_gate_apply(R* P, const int* cb, const i
             const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
             At[p * PL + c * LD + r] = pre[q];
         }
-        __syncthreads();                  // Q_j complete in LDS
+        lds_barrier();                  // Q_j complete in LDS
         if (j + 1 < j1) {
             const R* nxt = P + (long long)(j + 1) * mat;
 #pragma unroll
@@ -637,7 +647,7 @@ __global__ __launch_bounds__(256) void k_gate_apply(R* P, const int* cb, const i
                     dst[i * GT + c] = cr[a][b][v] + Bs[i * LD + c];
                     dst[GT * GT + i * GT + c] = ci[a][b][v] + Bs[PL + i * LD + c];
                 }
-        __syncthreads();                  // every wavefront is done with At
+        lds_barrier();                  // every wavefront is done with At
     }
 }
 

@@ -54,6 +54,16 @@ __constant__ float RK_F[MMAX] = {
     1.0f / 18, 1.0f / 19, 1.0f / 20, 1.0f / 21, 1.0f / 22, 1.0f / 23, 1.0f / 24, 1.0f / 25,
     1.0f / 26, 1.0f / 27, 1.0f / 28};
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also orders global memory, so it
+// waits for every global load in flight (a prefetch issued before it is then no prefetch);
+// this one waits for the LDS operations alone.  For loops whose threads exchange data
+// through LDS only, with every prefetched value consumed before the next barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ float rk_of(float, int k) { return RK_F[k]; }
 __device__ __forceinline__ double rk_of(double, int k) { return RK_D[k]; }
 
@@ -786,10 +796,16 @@ __global__ __launch_bounds__(512) void k_sp_boundary(BndArgs a) {
         if (grp == 0) a.Psi[pb + r] = v;
         else a.Lam[pb + (size_t)N * d + r] = v;
     }
+    // slice phases: the slice starts are floor(n K / N), so slice n holds K/N or K/N + 1 steps
+    const int Llo = a.K / N;
+    const double clo = cos(a.tau * sh * Llo), slo = sin(a.tau * sh * Llo);
+    const double chi = cos(a.tau * sh * (Llo + 1)), shi = sin(a.tau * sh * (Llo + 1));
     fetch(0);
+    // the loop's threads exchange the vectors through LDS only (Psi and Lambda are read back
+    // after the loop, past a full barrier), so its barriers leave the prefetch in flight
     for (int it = 0; it < N; ++it) {
         stage(it);
-        __syncthreads();                                 // staged matrices and xs visible
+        lds_barrier();                                   // staged matrices and xs visible
         if (it + 1 < N) fetch(it + 1);                  // next pair, consumed a step later
         const RM* Mf = STAGED ? ms + (size_t)(it & 1) * 4 * dd : Mb + (size_t)it * dd * 2;
         const RM* Ma = STAGED ? Mf + 2 * dd : Mb + (size_t)(N - 1 - it) * dd * 2;
@@ -813,12 +829,13 @@ __global__ __launch_bounds__(512) void k_sp_boundary(BndArgs a) {
                 }
             }
             // slice phase e^{-i theta_n} (forward) or e^{+i theta_n} (adjoint)
-            const double th = a.tau * sh * (double)(a.s[n + 1] - a.s[n]);
-            const double c0 = cos(th), s0 = grp == 0 ? -sin(th) : sin(th);
+            const int Ln = (int)(((long long)(n + 1) * a.K) / N - ((long long)n * a.K) / N);
+            const double c0 = Ln == Llo ? clo : chi, sv = Ln == Llo ? slo : shi;
+            const double s0 = grp == 0 ? -sv : sv;
             y.re = c0 * yr - s0 * yi;
             y.im = c0 * yi + s0 * yr;
         }
-        __syncthreads();                                 // every product has read xs
+        lds_barrier();                                   // every product has read xs
         if (r < d) {
             xs[grp * d + r] = y;
             if (grp == 0) a.Psi[pb + (size_t)(it + 1) * d + r] = y;
