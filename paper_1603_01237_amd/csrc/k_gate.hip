@@ -108,33 +108,50 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) cr[a][b][v] = ci[a][b][v] = 0;
-    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
-        // stage op(A)[i0:i0+64, k0:k0+KC] as As[k][i] and op(B)[k0:k0+KC, j0:j0+64] as Bs[k][j]
-        for (int q = t; q < GT * KC; q += 256) {
-            int i, k;
-            long long off;
-            if (!hA) {
-                i = q / KC; k = q % KC;
-                off = (long long)(i0 + i) * g.lda + (k0 + k);
-            } else {
-                k = q / GT; i = q % GT;
-                off = (long long)(k0 + k) * g.lda + (i0 + i);
-            }
-            As[0][k][i] = A[off];
-            As[1][k][i] = hA ? -A[off + g.pa] : A[off + g.pa];
-            int jj, kk;
-            long long offb;
-            if (!hB) {
-                kk = q / GT; jj = q % GT;
-                offb = (long long)(k0 + kk) * g.ldb + (j0 + jj);
-            } else {
-                jj = q / KC; kk = q % KC;
-                offb = (long long)(j0 + jj) * g.ldb + (k0 + kk);
-            }
-            Bs[0][kk][jj] = Bm[offb];
-            Bs[1][kk][jj] = hB ? -Bm[offb + g.pb] : Bm[offb + g.pb];
+    // op(A)[i0:i0+64, k0:k0+KC] is staged as As[k][i] and op(B)[k0:k0+KC, j0:j0+64] as
+    // Bs[k][j]; element q of a chunk (PQ per thread) is fetched into registers while the
+    // previous chunk runs on MFMA, and the loop's barriers order LDS only (the kernel's
+    // threads share nothing else: C never overlaps A or B), so the fetch stays in flight
+    constexpr int PQ = GT * KC / 256;
+    R far[PQ], fai[PQ], fbr[PQ], fbi[PQ];
+    auto a_ik = [&](int q, int& i, int& k) {
+        if (!hA) { i = q / KC; k = q % KC; } else { k = q / GT; i = q % GT; }
+    };
+    auto b_kj = [&](int q, int& kk, int& jj) {
+        if (!hB) { kk = q / GT; jj = q % GT; } else { jj = q / KC; kk = q % KC; }
+    };
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PQ; ++u) {
+            const int q = t + 256 * u;
+            int i, k, kk, jj;
+            a_ik(q, i, k);
+            b_kj(q, kk, jj);
+            const long long off = !hA ? (long long)(i0 + i) * g.lda + (k0 + k)
+                                      : (long long)(k0 + k) * g.lda + (i0 + i);
+            const long long offb = !hB ? (long long)(k0 + kk) * g.ldb + (j0 + jj)
+                                       : (long long)(j0 + jj) * g.ldb + (k0 + kk);
+            far[u] = A[off];
+            fai[u] = A[off + g.pa];
+            fbr[u] = Bm[offb];
+            fbi[u] = Bm[offb + g.pb];
         }
-        __syncthreads();
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < g.Kd; k0 += KC) {
+#pragma unroll
+        for (int u = 0; u < PQ; ++u) {
+            const int q = t + 256 * u;
+            int i, k, kk, jj;
+            a_ik(q, i, k);
+            b_kj(q, kk, jj);
+            As[0][k][i] = far[u];
+            As[1][k][i] = hA ? -fai[u] : fai[u];
+            Bs[0][kk][jj] = fbr[u];
+            Bs[1][kk][jj] = hB ? -fbi[u] : fbi[u];
+        }
+        lds_barrier();
+        if (k0 + KC < g.Kd) fetch(k0 + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
             const int kr = kk + (lane >> 4), li = lane & 15;
@@ -159,7 +176,7 @@ __global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
                     ci[a][b] = mfma16(ai[a], br[b], ci[a][b]);
                 }
         }
-        __syncthreads();
+        lds_barrier();
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
