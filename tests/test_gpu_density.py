@@ -60,6 +60,7 @@ CASES = [
     ("random_d4_K1_N1_single_step", lambda: _random_density(4, 1, 1, 9, T=0.05)),
     ("chain7_d128_K12_N3", lambda: _chain_density(7, 12, 3)),
     ("random_d4_K300_N1_scan", lambda: _random_density(4, 300, 1, 11)),
+    ("chain6_d64_K200_N2_scan64", lambda: _chain_density(6, 200, 2)),
     # dimensions that leave padding rows inside the gradient's column groups (d <= 32 packs
     # 64 / lpc columns per wavefront, lpc the least power of two >= d)
     ("random_d5_K40_N3_odd", lambda: _random_density(5, 40, 3, 13, alpha=0.1)),
