@@ -89,7 +89,7 @@ struct GemmArgs {
 };
 
 template <typename R, int KC>
-__global__ __launch_bounds__(256) void k_zgemm(GemmArgs g) {
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 2) void k_zgemm(GemmArgs g) {
     __shared__ R As[2][KC][GT + 1];   // [re/im][k][i]
     __shared__ R Bs[2][KC][GT + 1];   // [re/im][k][j]
     const GemmEntry e = g.e[blockIdx.y];
