@@ -712,6 +712,87 @@ __global__ __launch_bounds__(256) void k_gate_xy32(const R* RHS, const R* P, R* 
     }
 }
 
+// FP64 boundaries of density matrices for d <= 32, in one launch: workgroup 0 runs
+// Psi_{n+1} = W_n Psi_n W_n^+ for n = 0..N-1, workgroup 1 runs Lambda_n = W_n^+ Lambda_{n+1} W_n
+// for n = N-1..0 (PL = [Psi_0..Psi_N | Lambda_0..Lambda_N], W_n = M64 slot n).  The states are
+// zero outside their leading 32 x 32 block and the W_n the identity there, so the products
+// are formed on the blocks and every slot is written whole.  W for the next step is fetched
+// while the current sandwich runs on MFMA; the threads share data through LDS only.
+__global__ __launch_bounds__(256) void k_gate_dchain32(const double* M64, double* PL, int N) {
+    constexpr int BS = 32, LD = BS + 1, BP = BS * LD, PER = 2 * BS * BS / 256;
+    constexpr long long plane = (long long)GT * GT, mat = 2 * plane;
+    __shared__ double At[2 * BP], Bs[2 * BP], Ws[2 * BP];
+    const bool fwd = blockIdx.x == 0;
+    const int t = threadIdx.x;
+    const long long lam0 = (long long)(N + 1) * mat;
+    {
+        const double* S0 = PL + (fwd ? 0 : lam0 + (long long)N * mat);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            Bs[p * BP + r * LD + c] = S0[blk_gidx<BS>(e)];
+        }
+    }
+    double pre[PER];
+    auto fetch = [&](int n) {
+        const double* W = M64 + (long long)n * mat;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) pre[q] = W[blk_gidx<BS>(t + 256 * q)];
+    };
+    fetch(fwd ? 0 : N - 1);
+    for (int it = 0; it < N; ++it) {
+        const int n = fwd ? it : N - 1 - it;
+        // W_n row-major into Ws; the first product's left factor into At (At[k][i] = A[i][k]):
+        // A = W_n (forward) or W_n^+ (backward)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            const double v = pre[q];                       // W_n[r][c], plane p
+            Ws[p * BP + r * LD + c] = v;
+            if (fwd) At[p * BP + c * LD + r] = v;
+            else At[p * BP + r * LD + c] = p ? -v : v;
+        }
+        lds_barrier();                                     // W_n, At and the state in LDS
+        if (it + 1 < N) fetch(fwd ? it + 1 : N - 2 - it);
+        Acc<double>::T cr[1][1], ci[1][1];
+        blk_mm<double, BS>(At, Bs, cr, ci);                // T = A S
+        lds_barrier();                                     // every wavefront is done with At, Bs
+        // second product S' = T B2, B2 = W_n^+ (forward) or W_n (backward)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int i, c;
+            blk_rc<double, BS>(0, 0, v, i, c);
+            At[c * LD + i] = cr[0][0][v];
+            At[BP + c * LD + i] = ci[0][0][v];
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + 256 * q, p = e / (BS * BS), r = (e / BS) % BS, c = e % BS;
+            double v = fwd ? Ws[p * BP + c * LD + r] : Ws[p * BP + r * LD + c];
+            if (fwd && p) v = -v;
+            Bs[p * BP + r * LD + c] = v;
+        }
+        lds_barrier();                                     // T and B2 in LDS
+        blk_mm<double, BS>(At, Bs, cr, ci);
+        lds_barrier();                                     // every wavefront is done with At, Bs
+        double* dst = PL + (fwd ? (long long)(n + 1) * mat : lam0 + (long long)n * mat);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int i, c;
+            blk_rc<double, BS>(0, 0, v, i, c);
+            Bs[i * LD + c] = cr[0][0][v];
+            Bs[BP + i * LD + c] = ci[0][0][v];
+            dst[i * GT + c] = cr[0][0][v];
+            dst[plane + i * GT + c] = ci[0][0][v];
+        }
+        for (int e = t; e < (int)mat; e += 256) {          // zero outside the leading block
+            const int rc = e % (int)plane, r = rc / GT, c = rc % GT;
+            if (r >= BS || c >= BS) dst[e] = 0.0;
+        }
+        lds_barrier();                                     // the new state complete in Bs
+    }
+}
+
 // First step of every slice (blockIdx.y = n): [X | Y]^+ at step s_n is RHS_n^+ (RHS_n is
 // dp x 2dp planar, the output 2dp x dp planar).
 template <typename R>
