@@ -260,10 +260,12 @@ __device__ __forceinline__ int grad_order(const GateGen& gg, int j, int cap, dou
 // d <= 32, where lpc is the least power of two >= d and a workgroup of dp = 64 threads takes
 // 64 / lpc row blocks at once.  Entries of D_j outside the problem's rows and columns are
 // zero from the clear at create and are not written.
-template <typename R, int WT>
+// VS: row stride of the LDS vectors, dp rounded up to 64 or 256 (a 256-wide array at dp = 64
+// would hold 32 KB per one-wavefront workgroup and cap the residency at 5 per CU).
+template <typename R, int WT, int VS>
 __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long plane, int* flags,
                                                     int* kmax) {
-    __shared__ dcx vs[RB][256];
+    __shared__ dcx vs[RB * VS];
     const int j = blockIdx.x, t = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
     int lpc = dp;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
             for (int q = 0; q < RB; ++q) tr[q] = acc[q];
             for (int k = 0; k < m; ++k) {
 #pragma unroll
-                for (int q = 0; q < RB; ++q) vs[q][t] = tr[q];
+                for (int q = 0; q < RB; ++q) vs[q * VS + t] = tr[q];
                 __syncthreads();
                 const double rk = 1.0 / (k + 1);
 #pragma unroll
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
                     double ar = 0.0, ai = 0.0;
 #pragma unroll
                     for (int w = 0; w < WT; ++w) {
-                        const dcx x = vs[q][base + hc[w]];
+                        const dcx x = vs[q * VS + base + hc[w]];
                         ar = fma(hv[w].re, x.re, fma(-hv[w].im, x.im, ar));
                         ai = fma(hv[w].re, x.im, fma(hv[w].im, x.re, ai));
                     }
