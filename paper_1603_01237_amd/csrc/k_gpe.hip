@@ -123,13 +123,16 @@ __device__ __forceinline__ void dft16(Cd (&x)[16]) {
 struct Lds {
     double* sr;        // n + n/16: padded FFT exchange buffer, real plane
     double* si;        //           imaginary plane
-    double* kr;        // n: e^{-i tau k^2/2} / n
+    double* kr;        // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| = 0..n/2, rounded
     double* ki;
+    double* klr;       // n/2 + 1: its rounding residual (exact factor = kr + klr)
+    double* kli;
     double* tr;        // 768: [0,256) W_256^{r k}; [256,512) W_n^{16 r k}; [512,768) W_n^{r k}
     double* ti;
     double* red;       // 16
     __device__ __forceinline__ Cd tab(int i) const { return Cd{tr[i], ti[i]}; }
     __device__ __forceinline__ Cd kf(int i) const { return Cd{kr[i], ki[i]}; }
+    __device__ __forceinline__ Cd kfl(int i) const { return Cd{klr[i], kli[i]}; }
     __device__ __forceinline__ Cd ld(int i) const { return Cd{sr[i], si[i]}; }
     __device__ __forceinline__ void st(int i, Cd v) const {
         sr[i] = v.re;
@@ -143,9 +146,12 @@ __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
     Lds L;
     L.sr = reinterpret_cast<double*>(raw);
     L.si = L.sr + PN;
+    constexpr int KH = NN / 2 + 1;
     L.kr = L.si + PN;
-    L.ki = L.kr + NN;
-    L.tr = L.ki + NN;
+    L.ki = L.kr + KH;
+    L.klr = L.ki + KH;
+    L.kli = L.klr + KH;
+    L.tr = L.kli + KH;
     L.ti = L.tr + 768;
     L.red = L.ti + 768;
     return L;
@@ -215,7 +221,8 @@ struct GpeArgs {
     double V2;
     const dcx* tab;        // 768 FFT twiddles (FP64), layout of Lds::tab
     const dcx* Kh;         // n: e^{-i tau k^2/4} / n (FP64)
-    const dcx* Kf;         // n: e^{-i tau k^2/2} / n (FP64)
+    const dcx* Kf;         // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| 0..n/2 (FP64)
+    const dcx* Kfl;        // n/2 + 1: rounding residual of Kf (FP64)
     double* u;             // B*K
     dcx* Psi;              // B*(N+1)*n  psi(t_n)
     dcx* Lam;              // B*(N+1)*n  nu(t_n)
@@ -239,9 +246,11 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, double (&v
                                       double (&v1)[16]) {
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
-    for (int i = t; i < NN; i += T) {
+    for (int i = t; i <= NN / 2; i += T) {
         L.kr[i] = A.Kf[i].re;
         L.ki[i] = A.Kf[i].im;
+        L.klr[i] = A.Kfl[i].re;
+        L.kli[i] = A.Kfl[i].im;
     }
     for (int i = t; i < 768; i += T) {
         L.tr[i] = A.tab[i].re;
@@ -271,7 +280,11 @@ __device__ __forceinline__ double block_sum(double v, const Lds& L) {
 }
 
 // x <- F^-1 diag(k) F x, k at the owned frequencies: the fused kinetic factor from LDS
-// (kt == nullptr) or a table in global memory; CONJ uses conj(k) (adjoint kicks)
+// (kt == nullptr) or a table in global memory; CONJ uses conj(k) (adjoint kicks).  The fused
+// factor is applied as its rounded value plus the rounding residual: a rounded factor alone
+// makes the same relative error at every one of the K steps of a sweep, which adds up
+// coherently (about 5e-13 over 10^4 steps).  The factor depends on |frequency| only, so the
+// LDS holds the frequencies 0..n/2.
 template <int NN, bool CONJ>
 __device__ __forceinline__ void kick(Cd (&x)[16], const Lds& L, const Cd* kt) {
     constexpr int T = NN / 16;
@@ -279,8 +292,21 @@ __device__ __forceinline__ void kick(Cd (&x)[16], const Lds& L, const Cd* kt) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int m = threadIdx.x + T * i;
-        const Cd k = kt ? kt[m] : L.kf(m);
-        x[i] = CONJ ? cmulc(x[i], k) : cmul(x[i], k);
+        if (kt) {
+            const Cd k = kt[m];
+            x[i] = CONJ ? cmulc(x[i], k) : cmul(x[i], k);
+        } else {
+            const int mf = m <= NN / 2 ? m : NN - m;
+            const Cd k = L.kf(mf), kl = L.kfl(mf);
+            const Cd lo = CONJ ? cmulc(x[i], kl) : cmul(x[i], kl);
+            const Cd v = x[i];
+            if (CONJ)
+                x[i] = Cd{fma(v.re, k.re, fma(v.im, k.im, lo.re)),
+                          fma(v.im, k.re, fma(-v.re, k.im, lo.im))};
+            else
+                x[i] = Cd{fma(v.re, k.re, fma(-v.im, k.im, lo.re)),
+                          fma(v.im, k.re, fma(v.re, k.im, lo.im))};
+        }
     }
     fft<NN, 1>(x, L);
 }
@@ -503,6 +529,7 @@ struct GpeExt {
     dcx* tab = nullptr;
     dcx* Kh = nullptr;
     dcx* Kf = nullptr;
+    dcx* Kfl = nullptr;
     dcx* Psi = nullptr;
     dcx* Lam = nullptr;
     dcx* psi0 = nullptr;
@@ -517,7 +544,7 @@ static void gpe_free(ism_problem* p) {
 
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision) {
     const size_t rs = precision == ISM_FP64 ? 16 : 8;
-    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 768) * 16;
+    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 2 + 768) * 16;
 }
 
 static GpeArgs gpe_args(ism_problem* p) {
@@ -537,6 +564,7 @@ static GpeArgs gpe_args(ism_problem* p) {
     A.tab = x->tab;
     A.Kh = x->Kh;
     A.Kf = x->Kf;
+    A.Kfl = x->Kfl;
     A.u = p->u;
     A.Psi = x->Psi;
     A.Lam = x->Lam;
@@ -552,7 +580,8 @@ static GpeArgs gpe_args(ism_problem* p) {
 // exchange buffer (padded), kinetic factors, twiddle tables, reduction slots; FP64 in both
 // precisions
 static size_t gpe_shmem(int n) {
-    return ((size_t)n + n / 16 + n + 768) * sizeof(dcx) + 16 * sizeof(double);
+    return ((size_t)n + n / 16 + (size_t)n / 2 + 1 + 768) * sizeof(dcx) +
+           2 * ((size_t)n / 2 + 1) * sizeof(double) + 16 * sizeof(double);
 }
 
 template <typename R>
@@ -651,30 +680,45 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
     if ((st = dev_upload(p, (void**)&x->V1, V1, n * sizeof(double)))) return st;
     if ((st = dev_upload(p, (void**)&x->psi0, psi0, n * sizeof(dcx)))) return st;
     if ((st = dev_upload(p, (void**)&x->target, target, n * sizeof(dcx)))) return st;
-    const double PI = 3.14159265358979323846;
-    // twiddles e^{-2 pi i e/m} with the exponent reduced exactly, in FP64
+    // Tables, each entry computed in extended precision (x87 long double) and rounded once
+    // to FP64.  Twiddles e^{-2 pi i e/m} with the exponent reduced exactly.
+    const long double PIL = 3.141592653589793238462643383279502884L;
     auto root = [&](long long e, long long m) {
         e %= m;
-        return dcx{cos(2 * PI * (double)e / (double)m), -sin(2 * PI * (double)e / (double)m)};
+        const long double a = 2.0L * PIL * (long double)e / (long double)m;
+        return dcx{(double)cosl(a), (double)-sinl(a)};
     };
-    std::vector<dcx> tab(768), kh(n), kf(n);
+    std::vector<dcx> tab(768), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
     for (int r = 0; r < 16; ++r)
         for (int k = 0; k < 16; ++k) {
             tab[r * 16 + k] = root((long long)r * k, 256);              // pass 2
             tab[256 + r * 16 + k] = root(16LL * r * k, n);              // pass 3, high part
             tab[512 + r * 16 + k] = root((long long)r * k, n);          // pass 3, low part
         }
+    // wavenumbers k_f = 2 pi f / (n dx) in FP64, formed as (2 pi) (f (1 / (n dx))) with
+    // dx = L / n (the grid's frequencies in the usual fftfreq order); the kinetic phase
+    // -tau k^2 / 4 and its exponential are then evaluated in extended precision
+    const double dxd = L / n, fscale = 1.0 / (n * dxd), twopi = 2 * 3.141592653589793;
+    auto phase_of = [&](int f) {
+        const double k = twopi * ((double)f * fscale);
+        return -(long double)p->tau * (long double)k * (long double)k / 4.0L;
+    };
     for (int m = 0; m < n; ++m) {
         const int f = m < n / 2 ? m : m - n;            // fftfreq ordering
-        const double k = 2 * PI * f / L;
-        const double ph = -p->tau * k * k / 4;
-        kh[m] = dcx{cos(ph) / n, sin(ph) / n};
-        kf[m] = dcx{cos(2 * ph) / n, sin(2 * ph) / n};
+        const long double ph = phase_of(f);
+        kh[m] = dcx{(double)(cosl(ph) / n), (double)(sinl(ph) / n)};
+    }
+    for (int m = 0; m <= n / 2; ++m) {                  // |frequency| m (the factor is even)
+        const long double ph = 2.0L * phase_of(m == n / 2 ? -m : m);
+        const long double cr = cosl(ph) / n, ci = sinl(ph) / n;
+        kf[m] = dcx{(double)cr, (double)ci};
+        kfl[m] = dcx{(double)(cr - (long double)kf[m].re), (double)(ci - (long double)kf[m].im)};
     }
     const bool f64 = p->precision == ISM_FP64;
     if ((st = dev_upload(p, (void**)&x->tab, tab.data(), tab.size() * sizeof(dcx)))) return st;
     if ((st = dev_upload(p, (void**)&x->Kh, kh.data(), kh.size() * sizeof(dcx)))) return st;
     if ((st = dev_upload(p, (void**)&x->Kf, kf.data(), kf.size() * sizeof(dcx)))) return st;
+    if ((st = dev_upload(p, (void**)&x->Kfl, kfl.data(), kfl.size() * sizeof(dcx)))) return st;
     const size_t nb = (size_t)p->B * (p->N + 1) * n * sizeof(dcx);
     if ((st = dev_alloc(p, (void**)&x->Psi, nb))) return st;
     if ((st = dev_alloc(p, (void**)&x->Lam, nb))) return st;

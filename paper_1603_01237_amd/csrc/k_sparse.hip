@@ -79,6 +79,24 @@ __device__ __forceinline__ double lane_fetch(int addr, double v) {
                                             (unsigned long long)(unsigned)lo));
 }
 
+// (cos theta, sin theta) of the slice phase theta = tau s L.  The angle is carried as an
+// unevaluated sum hi + lo: tau s and its product with L are formed together with their exact
+// rounding errors (fma), so the angle is exact to ~1e-31 relative before cos and sin see it.
+// A plain tau * s * L is off by up to an ulp of theta (4e-15 at theta ~ 20 on the rotor),
+// the same for every slice of equal length, and those errors add up over the slices into
+// the global phase of psi(T) (2.7e-13 on the rotor batch at K = 20000).
+__device__ __forceinline__ void slice_phase(double tau, double s, int L, double* c, double* sn) {
+    const double p = tau * s;
+    const double pe = fma(tau, s, -p);                  // tau s = p + pe
+    const double h = p * (double)L;
+    const double he = fma(p, (double)L, -h);            // p L = h + he
+    const double lo = he + pe * (double)L;
+    double sh, ch;
+    sincos(h, &sh, &ch);
+    *c = fma(-sh, lo, ch);
+    *sn = fma(ch, lo, sh);
+}
+
 // Row exchange between the lanes that hold one item.
 //  XWave : d <= 64, several items per wavefront; a neighbour row is read straight from the
 //          other lane's register (ds_bpermute), so publish/sync are no-ops and `addr` is the
@@ -543,8 +561,8 @@ __global__ __launch_bounds__(256) void k_sp_slice(SpArgs a) {
         ci = (R)ph.im;
     }
     R pr = xr, pi = xi;
-    const double theta = a.tau * sh * (double)L;
-    const double cph = cos(theta), sph = sin(theta);   // e^{-i theta} = cph - i sph
+    double cph, sph;                                   // e^{-i theta} = cph - i sph
+    slice_phase(a.tau, sh, L, &cph, &sph);
     const double beta_over_tau = ((double)a.K / (double)L) / a.tau;
     const bool upd = a.update && (a.active == nullptr || a.active[im.b] != 0);
     fetch_controls<CGM>(a, im.b, sn + (a.LMAX - 1 < L ? a.LMAX - 1 : L - 1), unext);
@@ -798,8 +816,9 @@ __global__ __launch_bounds__(512) void k_sp_boundary(BndArgs a) {
     }
     // slice phases: the slice starts are floor(n K / N), so slice n holds K/N or K/N + 1 steps
     const int Llo = a.K / N;
-    const double clo = cos(a.tau * sh * Llo), slo = sin(a.tau * sh * Llo);
-    const double chi = cos(a.tau * sh * (Llo + 1)), shi = sin(a.tau * sh * (Llo + 1));
+    double clo, slo, chi, shi;
+    slice_phase(a.tau, sh, Llo, &clo, &slo);
+    slice_phase(a.tau, sh, Llo + 1, &chi, &shi);
     fetch(0);
     // the loop's threads exchange the vectors through LDS only (Psi and Lambda are read back
     // after the loop, past a full barrier), so its barriers leave the prefetch in flight
@@ -986,9 +1005,23 @@ __device__ __forceinline__ void tri_coeffs(const SpArgs& a, int b, int r0, bool 
     for (int q = 0; q < RPL; ++q) {
         const int r = r0 + q;
         const bool ok = valid && r < a.d;
-        const double dd = ok ? (a.h0diag[(size_t)b * a.h0diag_stride + r] - sh) * ts : 0.0;
+        const double hv = ok ? a.h0diag[(size_t)b * a.h0diag_stride + r] : sh;
+        const double df = hv - sh;
+        const double dd = df * ts;
         dg[q] = (R)dd;
-        dl[q] = (R)(dd - (double)dg[q]);
+        if (sizeof(R) == 4) {
+            dl[q] = (R)(dd - (double)dg[q]);
+        } else {
+            // FP64: the residual of the exact (h - s) tau / nsub against dd, from the exact
+            // rounding errors of the difference (two-sum), of the product (fma) and of the
+            // sub-step length ts = tau / nsub
+            const double bv = df - hv, av = df - bv;
+            const double e1 = (hv - av) + (-sh - bv);
+            const double e2 = fma(df, ts, -dd);
+            const double ns = rint(a.tau / ts);
+            const double rts = fma(-ns, ts, a.tau) / ns;
+            dl[q] = (R)(e2 + e1 * ts + df * rts);
+        }
         double lv = 0.0, rv = 0.0;
         if (ok) {
             for (int w = 0; w < a.WC; ++w) {
@@ -1397,6 +1430,10 @@ __global__ __launch_bounds__(256) void k_sp_assemble_tri(SpArgs a) {
         }
     }
     if (sizeof(R) == 4 && pend > 0) tri_phase(xr, xi, dl, (R)pend);
+    // FP64: the diagonal's residual is the same at every sub-step; the phase it builds up over
+    // the slice (twice the residual per step for the Cayley map) is applied once here, where it
+    // is large enough to survive rounding (~1e-15 against ~1e-17 per step)
+    if (sizeof(R) == 8) tri_phase(xr, xi, dl, (R)(a.cn ? 2 * L : L * S));
     if (valid) {
         R* M = reinterpret_cast<R*>(a.M);
         const size_t o = (((size_t)b * a.N + n) * d + col) * d;
@@ -1485,8 +1522,8 @@ __global__ __launch_bounds__(256) void k_sp_slice_tri(SpArgs a) {
             ci[q] = (R)ph.im;
         }
     }
-    const double theta = a.tau * a.shift[b] * (double)L;
-    const double cph = cos(theta), sph = sin(theta);   // e^{-i theta} = cph - i sph
+    double cph, sph;                                   // e^{-i theta} = cph - i sph
+    slice_phase(a.tau, a.shift[b], L, &cph, &sph);
     const double beta_over_tau = ((double)a.K / (double)L) / a.tau;
     const bool upd = a.update && (a.active == nullptr || a.active[b] != 0);
     unext = ub[sn + (a.LMAX - 1 < L ? a.LMAX - 1 : L - 1)];

@@ -1,8 +1,7 @@
 """GPU parity of the dense gate path (batched complex GEMM on MFMA) against the FP64 oracle.
 
 Gate synthesis: psi0 = I, target W, <A|B> = Tr(A^+ B)/d (evolution-operator form of Sec. 2).
-Tolerances as for the state path: FP64 relative L2 <= 1e-12 (grows as 2e-14 sqrt(K) beyond
-K = 2500), FP32 mixed ||U_gpu(T) - U_ref(T)||_F / sqrt(d) <= 1e-4 and gradient relative L2
+Tolerances as for the state path: FP64 relative L2 <= 1e-12 at every size, FP32 mixed ||U_gpu(T) - U_ref(T)||_F / sqrt(d) <= 1e-4 and gradient relative L2
 <= 1e-3.
 """
 import sys
@@ -96,7 +95,8 @@ def test_gate_iterate_equals_plain():
 
 def test_gate_full_size_sampled():
     """8-spin chain gate synthesis at its full size (d=256, 16 controls, K=2000, N=64):
-    U(T) against the oracle's product of step exponentials; the gradient at sampled steps."""
+    U(T) against the oracle's product of step exponentials (FP64 relative 1e-12); the gradient
+    at one step of every slice (FP64 relative 1e-12 per step)."""
     _say("case gate full size")
     P = _P()
     p = problems.spin_chain_gate()
@@ -116,15 +116,21 @@ def test_gate_full_size_sampled():
         errU = np.linalg.norm(UT - UK) / np.sqrt(p.d)
         _say(prec, "U(T) err", errU)
         if prec == "fp64":
-            assert _rel(UT, UK) <= max(1e-12, 2e-14 * np.sqrt(p.K))
+            assert _rel(UT, UK) <= 1e-12
         else:
             assert errU <= 1e-4
-    for j in (0, 31, 1000, 1999):
+    # one step in every slice, at a different position in each (n mod the slice length), and
+    # the last step
+    s = O.slice_starts(p.K, p.N)
+    steps = [int(s[n] + n % (s[n + 1] - s[n])) for n in range(p.N)] + [p.K - 1]
+    worst = [0.0, 0.0]
+    for j in steps:
         Hh = O.hhat(O.hamiltonian(p.H0, p.Hc, u[j]), p.Hc, tau)
         gref = np.array([np.trace(lams[j].conj().T @ Hh[c] @ psis[j]).imag / p.d
                          for c in range(p.C)])
         e64 = _rel(res["fp64"][1][j], gref)
         e32 = _rel(res["fp32"][1][j], gref)
-        _say("step", j, "fp64 g err", e64, "fp32 g err", e32)
-        assert e64 <= 1e-10
-        assert e32 <= 1e-3
+        worst = [max(worst[0], e64), max(worst[1], e32)]
+        assert e64 <= 1e-12, (j, e64)
+        assert e32 <= 1e-3, (j, e32)
+    _say("gradient over", len(steps), "steps: fp64 worst", worst[0], "fp32 worst", worst[1])

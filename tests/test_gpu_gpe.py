@@ -1,11 +1,13 @@
 """GPU parity of the Gross-Pitaevskii path (Strang splitting with the LDS-resident FFT,
 exact nonlinear adjoint, BEC-variant ISM) against the FP64 oracle.
 
-Norms use the grid measure: ||f|| = sqrt(dx sum |f|^2).  FP64: relative <= 1e-12 (K <= 2500),
-growing as 2e-14 sqrt(K) beyond; FP32 mixed: ||psi_gpu(T) - psi_ref(T)|| <= 1e-4 and gradient
-relative L2 <= 1e-3.
+Norms use the grid measure: ||f|| = sqrt(dx sum |f|^2).  FP64: 1e-12 (relative for the
+gradient) on the small cases; at the full size (K = 10^4) the measured FP64 drift of a plain
+FP64 evaluation (see test_gpe_full_size).  FP32 mixed: ||psi_gpu(T) - psi_ref(T)|| <= 1e-4 and
+gradient relative L2 <= 1e-3.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -101,13 +103,24 @@ def test_gpe_iterate_equals_plain():
     assert np.max(np.abs(u - ref["u"])) <= 1e-12
 
 
-def test_gpe_full_size_sampled():
+def test_gpe_full_size():
     """The condensate workload at its full size: n=4096 on [-20,20), g=10, K=10000, N=64,
-    ground states at x0=0 and x0=5; psi(T), J, F and the gradient against the oracle."""
+    ground states at x0=0 and x0=5; psi(T), J, F and the gradient against the oracle's values
+    (tests/golden/gpe_n4096_k10000.npz, written by make_gpe_reference.py).
+
+    FP64 bars: those of a plain FP64 evaluation of the same sweep, measured on the CPU in
+    test_oracle_long.py::test_gpe_plain_fp64_drift_full_size (psi(T) 1.9e-11, gradient 5.9e-10
+    relative): the rounding of a slowly varying state repeats at every one of the 4 x 10^4
+    transforms and adds up linearly, at any FP64 implementation.  Measured here: psi(T)
+    7.9e-12, gradient 2.8e-10 against the oracle (psi(T) 7.9e-12 against an all-extended
+    evaluation, which the oracle matches to 1.1e-14)."""
     _say("case gpe full size")
     P = _P()
     p = problems.gpe()
     dx = p.dx
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "gpe_n4096_k10000.npz"))
+    psiK, Jr, Fr, gr = ref["psiT"], float(ref["J"]), float(ref["F"]), ref["g"]
     res = {}
     for prec in ("fp32", "fp64"):
         with P.from_problem(p, precision=prec) as h:
@@ -116,23 +129,12 @@ def test_gpe_full_size_sampled():
             g = h.gradient()[0, :, 0]
         res[prec] = (psiT, J[0], F[0], g)
         _say(prec, "gpu done")
-    gr, Jr, Fr, psiK = _oracle(p)
-    # FP64 bar derived from the arithmetic: every transform of a step carries a fixed error
-    # of at most log2(n) unit roundoffs from its rounded twiddles, the same at every step, so
-    # the two implementations (this FFT and the oracle's) drift apart coherently over the
-    # 2K transforms of a sweep (and 2K more in the adjoint):
-    u64 = 2.0 ** -53
-    tol_state = 4 * u64 * p.K * math.log2(p.n)
-    # gradient g_j = dx sum dV/du Im(conj(nu') b): by Cauchy-Schwarz its error is at most
-    # 2 max|dV/du| times the state error, relative to the rms gradient
-    dV = np.abs(p.V1[:, None] + 2 * p.u0[0, None, :, 0] * p.V2)
-    tol_g = 2 * float(dV.max()) * tol_state / float(np.sqrt(np.mean(gr ** 2)))
     for prec, (psiT, J, F, g) in res.items():
         e_psi = _norm(psiT - psiK, dx)
         e_g = np.linalg.norm(g - gr) / np.linalg.norm(gr)
-        _say(prec, "psi err", e_psi, "J err", abs(J - Jr), "g rel err", e_g,
-             "fp64 bars", tol_state, tol_g)
+        _say(prec, "psi err", e_psi, "J err", abs(J - Jr), "F err", abs(F - Fr), "g rel err", e_g)
         if prec == "fp64":
-            assert e_psi <= tol_state and abs(J - Jr) <= tol_state and e_g <= tol_g
+            assert e_psi <= 2e-11 and abs(J - Jr) <= 2e-11 and abs(F - Fr) <= 2e-11
+            assert e_g <= 6e-10
         else:
             assert e_psi <= 1e-4 and abs(F - Fr) <= 1e-4 and e_g <= 1e-3

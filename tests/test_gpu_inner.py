@@ -173,12 +173,11 @@ def test_inner_argument_checks():
 def test_inner_rotor_full_size_sampled():
     """The benchmark's rotor batch (256 rotors, K=20000, N=128), one iteration with two
     gradient steps per slice problem and Err, FP32 mixed and FP64; two instances checked
-    against the oracle.  FP64 bar as for the single-step path at this K (random-walk
-    rounding, 2e-14 sqrt(K))."""
+    against the oracle.  FP64 bar 1e-12, as for the single-step path at this K."""
     from paper_1603_01237_amd import _lib
     _say("case inner rotor full size")
     p = problems.rotor()
-    tol64 = max(1e-12, 2e-14 * np.sqrt(p.K))
+    tol64 = 1e-12
     res = {}
     for prec in ("fp32", "fp64"):
         with _lib.from_problem(p, precision=prec) as h:

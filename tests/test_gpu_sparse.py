@@ -1,14 +1,14 @@
 """GPU parity of the sparse state path (path (b)) against the FP64 oracle, through the C ABI.
 
 Tolerances (per instance, norms over the whole output):
-  FP64 path      : relative L2 <= tol64(K) = max(1e-12, 2e-14 sqrt(K)) on psi(T), g, J, u
-                   (1e-10 on u after 50 iterations).  Two independent FP64 evaluations of the
-                   exponential step map (eigendecomposition vs Pade scaling-and-squaring) of the
-                   stiff rotor generator (||H|| ~ 500, ||tau H|| ~ 0.25) already differ by
-                   ~1.5e-13 after 4000 steps, growing like sqrt(K): rounding of unitary steps
-                   adds up as a random walk.  tol64 is 1e-12 for K <= 2500.
+  FP64 path      : relative L2 <= 1e-12 on psi(T), lambda(0), g, J and F at every size, the
+                   benchmark's K = 20000 included; 1e-10 on the controls and J after 50
+                   iterations.  The oracle's own share of the budget at K = 20000 is pinned on
+                   the CPU (tests/test_oracle_long.py: within 5e-14 of an extended-precision
+                   evaluation; measured 2.7e-14 over the 256 rotors).
   FP32 mixed path: ||psi_gpu(T) - psi_ref(T)||_2 <= 1e-4, ||g_gpu - g_ref|| / ||g_ref|| <= 1e-3
 """
+import os
 import sys
 
 import numpy as np
@@ -34,8 +34,8 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def tol64(K):
-    return max(1e-12, 2e-14 * np.sqrt(K))
+TOL64 = 1e-12
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rotor_b256_k20000.npz")
 
 
 def _oracle_grad(p, b, u):
@@ -88,7 +88,7 @@ def test_fp64_forward_gradient_parity(name, mk):
     for b in range(p.batch):
         gr, Jr, Fr, psiK = _oracle_grad(p, b, p.u0[b])
         lam0 = O.backward(O.step_unitaries(p.H0_of(b), p.Hc, p.u0[b], p.T / p.K), p.target)[0]
-        assert _rel(psiT[b], psiK) <= 1e-12
+        assert _rel(psiT[b], psiK) <= TOL64
         assert _rel(chi0[b], lam0) <= 1e-12
         assert abs(J[b] - Jr) <= 1e-12 and abs(F[b] - Fr) <= 1e-12
         assert _rel(g[b], gr) <= 1e-12, _rel(g[b], gr)
@@ -203,32 +203,40 @@ def test_device_io_matches_host_io():
     assert np.array_equal(psi_dev.cpu().numpy(), psi_host)
 
 
-def test_rotor_full_size_sampled():
+def test_rotor_full_size():
     """The benchmark's launch configuration (256 rotors, K=20000, N=128), FP32 mixed and
-    FP64; two instances are checked against the oracle one by one."""
+    FP64.  psi(T), lambda(0), J and F of every instance against the oracle's values
+    (tests/golden/rotor_b256_k20000.npz, written by make_rotor_reference.py from the oracle);
+    the full gradient of instances 0, 127 and 255 against the oracle computed here."""
     _say("case rotor full size")
     P = _P()
     p = problems.rotor()
+    ref = np.load(GOLDEN)
     res = {}
     for prec in ("fp32", "fp64"):
         with P.from_problem(p, precision=prec) as h:
             g = h.gradient()
             psiT = h.forward()
-        res[prec] = (g, psiT)
-    for b in (0, 255):
+            lam0 = h.adjoint()
+            J, F = h.fidelity()
+        res[prec] = (g, psiT, lam0, J, F)
+    g64, psi64, lam64, J64, F64 = res["fp64"]
+    g32, psi32, lam32, J32, F32 = res["fp32"]
+    e_psi = np.linalg.norm(psi64 - ref["exp_psiT"], axis=1)
+    e_lam = np.linalg.norm(lam64 - ref["exp_lam0"], axis=1)
+    e32 = np.linalg.norm(psi32 - ref["exp_psiT"], axis=1)
+    _say("fp64 psi(T) max", e_psi.max(), "lambda(0) max", e_lam.max(),
+         "J max", np.abs(J64 - ref["exp_J"]).max(), "F max", np.abs(F64 - ref["exp_F"]).max(),
+         "| fp32 psi(T) max", e32.max(), "F max", np.abs(F32 - ref["exp_F"]).max())
+    assert e_psi.max() <= TOL64 and e_lam.max() <= TOL64
+    assert np.abs(J64 - ref["exp_J"]).max() <= TOL64 and np.abs(F64 - ref["exp_F"]).max() <= TOL64
+    assert e32.max() <= 1e-4 and np.abs(F32 - ref["exp_F"]).max() <= 1e-4
+    for b in (0, 127, 255):
         gr, Jr, Fr, psiK = _oracle_grad(p, b, p.u0[b])
-        g64, psi64 = res["fp64"][0][b], res["fp64"][1][b]
-        g32, psi32 = res["fp32"][0][b], res["fp32"][1][b]
-        _say("instance", b, "fp64 g", _rel(g64, gr), "psi", _rel(psi64, psiK),
-             "fp32 g", _rel(g32, gr), "psi", np.linalg.norm(psi32 - psiK))
-        assert _rel(psi64, psiK) <= tol64(p.K)
-        assert _rel(g64, gr) <= tol64(p.K)
-        assert np.linalg.norm(psi32 - psiK) <= 1e-4
-        assert _rel(g32, gr) <= 1e-3
-    # every instance: unit norm of psi(T) and finite gradients
-    for prec, tol in (("fp32", 1e-4), ("fp64", tol64(p.K))):
-        assert np.all(np.abs(np.linalg.norm(res[prec][1], axis=1) - 1) <= tol)
-        assert np.all(np.isfinite(res[prec][0]))
+        _say("instance", b, "fp64 g", _rel(g64[b], gr), "fp32 g", _rel(g32[b], gr))
+        assert _rel(g64[b], gr) <= TOL64
+        assert _rel(g32[b], gr) <= 1e-3
+    assert np.all(np.isfinite(g64)) and np.all(np.isfinite(g32))
 
 
 def test_taylor_params_per_instance():
