@@ -193,6 +193,25 @@ int ism_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double*
                 int* iters_done);
 
 /*
+ * Allocation-free ism_iterate, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.  Same arguments,
+ * stopping rule, kernels and results as ism_iterate (bitwise, for the same handle state);
+ * the J history the boundary kernels write lives in a fixed device array of the library,
+ * ISM_STATIC_HIST_MAX doubles (1 MiB) on each GPU it runs on, held until the process ends,
+ * instead of a buffer grown per handle; flags are cleared by a kernel, not a host copy.
+ * The call allocates no device or host memory (the handle's buffers come from create).
+ *   - ISM_E_BUDGET if max(n_iter, 1) * batch > ISM_STATIC_HIST_MAX; nothing runs.
+ *   - J_hist receives the rows the loop wrote, J^(k) for k < *iters_done and the row of the
+ *     iteration that stopped the loop early; later rows are left untouched.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap on a GPU (from
+ *     several host threads, or on streams whose work runs concurrently) race.  Each call
+ *     writes its rows before it reads them, so nothing from an earlier call is read.
+ */
+#define ISM_STATIC_HIST_MAX 131072
+int ism_iterate_static(ism_problem* p, int n_iter, double rho, double fid_stop, double* J_hist,
+                       int* iters_done);
+
+/*
  * ISM iterations with several gradient steps per slice problem and the Err stopping rule
  * (Algorithm 1, steps (c) and (e); Eq. (gradStep) iterated).  Iteration k rebuilds the
  * boundaries and intermediate states phi^(k) at u^(k) (steps (a)-(b)), then every slice n

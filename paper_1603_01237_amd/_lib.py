@@ -25,11 +25,12 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
 EXPORTED = [
     "ism_default_options", "ism_problem_create", "ism_problem_create_gpe", "ism_problem_destroy",
     "ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient",
-    "ism_iterate", "ism_iterate_inner", "ism_fidelity", "ism_problem_info", "ism_taylor_params", "ism_status_string", "ism_problem_footprint",
+    "ism_iterate", "ism_iterate_inner", "ism_iterate_static", "ism_fidelity", "ism_problem_info", "ism_taylor_params", "ism_status_string", "ism_problem_footprint",
     "ism_set_timing", "ism_kernel_times",
     "ism_server_clock", "ism_server_create", "ism_server_submit", "ism_server_progress",
     "ism_server_poll", "ism_server_take", "ism_server_stats_get", "ism_server_destroy",
 ]
+ISM_STATIC_HIST_MAX = 131072       # doubles in the fixed J-history array of ism_iterate_static
 REQ_FINITE, REQ_GPE = 0, 1
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 
@@ -113,6 +114,8 @@ def lib():
                  "ism_gradient"):
         getattr(L, name).argtypes = [vp, vp]
     L.ism_iterate.argtypes = [vp, ct.c_int, ct.c_double, ct.c_double, vp, ct.POINTER(ct.c_int)]
+    L.ism_iterate_static.argtypes = [vp, ct.c_int, ct.c_double, ct.c_double, vp,
+                                     ct.POINTER(ct.c_int)]
     L.ism_iterate_inner.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_double,
                                     vp, vp, ct.POINTER(ct.c_int)]
     L.ism_fidelity.argtypes = [vp, vp, vp]
@@ -143,7 +146,7 @@ def lib():
         getattr(L, name).restype = ct.c_int
     for name in ("ism_problem_create", "ism_problem_create_gpe", "ism_set_controls",
                  "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient", "ism_iterate",
-                 "ism_iterate_inner", "ism_fidelity", "ism_problem_info"):
+                 "ism_iterate_inner", "ism_iterate_static", "ism_fidelity", "ism_problem_info"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -318,6 +321,21 @@ class Problem:
         _check(lib().ism_iterate(self._h, int(n_iter), float(rho), float(fid_stop),
                                  self._ptr(Jh) if Jh is not None else None, ct.byref(done)),
                "ism_iterate")
+        if Jh is not None:
+            Jh = Jh[:n_iter]
+        return Jh, done.value
+
+    def iterate_static(self, n_iter, rho, fid_stop=2.0, record=True):
+        """ism_iterate_static: as iterate, with the J history in the library's fixed device
+        array (no allocation).  Rows past the ones the call wrote are NaN."""
+        Jh = self._out((max(n_iter, 1), self.B), np.float64) if record else None
+        if Jh is not None:
+            Jh[...] = np.nan
+        done = ct.c_int(0)
+        _check(lib().ism_iterate_static(self._h, int(n_iter), float(rho), float(fid_stop),
+                                        self._ptr(Jh) if Jh is not None else None,
+                                        ct.byref(done)),
+               "ism_iterate_static")
         if Jh is not None:
             Jh = Jh[:n_iter]
         return Jh, done.value

@@ -649,24 +649,58 @@ int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, doubl
         p->Jhist = nh;
         p->Jhist_cap = (int)need;
     }
-    const bool err_rule = err_stop > 0.0;
-    const bool want_err = err_rule || Err_hist != nullptr;
+    const bool want_err = err_stop > 0.0 || Err_hist != nullptr;
     if (want_err && (size_t)p->Errhist_cap < need) {
         double* nh = nullptr;
         if ((st = dev_alloc(p, (void**)&nh, need * sizeof(double)))) return st;
         p->Errhist = nh;
         p->Errhist_cap = (int)need;
     }
-    std::vector<int> ones(p->B, 1);
-    ISM_TRY_HIP(hipMemcpyAsync(p->active, ones.data(), p->B * sizeof(int), hipMemcpyHostToDevice,
-                               p->stream));
-    ISM_TRY_HIP(hipMemsetAsync(p->flags, 0, 4 * sizeof(int), p->stream));
+    int done = 0;
+    if ((st = iterate_loop(p, n_iter, n_inner, rho, fid_stop, err_stop, p->Jhist,
+                           want_err ? p->Errhist : nullptr, false, &done)))
+        return st;
+    if (J_hist && n_iter > 0) {
+        if ((st = copy_out(p, J_hist, p->Jhist, (size_t)n_iter * p->B * sizeof(double)))) return st;
+    }
+    if (Err_hist && done > 0) {
+        if ((st = copy_out(p, Err_hist, p->Errhist, (size_t)done * p->B * sizeof(double)))) return st;
+    }
+    if (iters_done) *iters_done = done;
+    return ISM_OK;
+}
+
+}  // extern "C"
+
+namespace ism {
+
+// The iteration loop of Algorithm 1 (steps (a)-(e)) on history buffers the caller provides:
+// jbuf holds n_iter * B doubles, ebuf (null unless Err is wanted) as many.  With `fills` the
+// active flags and counters are set by a fill kernel rather than a host copy and
+// hipMemsetAsync, so the loop touches no host memory besides the flags it reads back.
+int iterate_loop(ism_problem* p, int n_iter, int n_inner, double rho, double fid_stop,
+                 double err_stop, double* jbuf, double* ebuf, bool fills, int* done_out) {
+    int st;
+    const bool err_rule = err_stop > 0.0;
+    if (fills) {
+        ISM_TRY_HIP(launch_fill_i32(p->active, 1, p->B, p->stream));
+        ISM_TRY_HIP(launch_fill_i32(p->flags, 0, 4, p->stream));
+    } else {
+        std::vector<int> ones(p->B, 1);
+        ISM_TRY_HIP(hipMemcpyAsync(p->active, ones.data(), p->B * sizeof(int),
+                                   hipMemcpyHostToDevice, p->stream));
+        ISM_TRY_HIP(hipStreamSynchronize(p->stream));      // `ones` is pageable and goes out of scope
+        ISM_TRY_HIP(hipMemsetAsync(p->flags, 0, 4 * sizeof(int), p->stream));
+    }
     const bool check_stop = fid_stop <= 1.0 || err_rule;
     int done = 0;
     for (int k = 0; k < n_iter; ++k) {
-        if (check_stop) ISM_TRY_HIP(hipMemsetAsync(p->flags + 1, 0, sizeof(int), p->stream));
+        if (check_stop) {
+            if (fills) ISM_TRY_HIP(launch_fill_i32(p->flags + 1, 0, 1, p->stream));
+            else ISM_TRY_HIP(hipMemsetAsync(p->flags + 1, 0, sizeof(int), p->stream));
+        }
         // steps (a)-(b): boundaries and intermediate states at u^(k)
-        if ((st = boundary_pass(p, p->Jhist + (size_t)k * p->B, fid_stop, true))) return st;
+        if ((st = boundary_pass(p, jbuf + (size_t)k * p->B, fid_stop, true))) return st;
         if (check_stop) {
             int fl[4];
             if ((st = read_flags(p, fl))) return st;
@@ -680,13 +714,13 @@ int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, doubl
             if ((st = slice_pass(p, 1, rho, nullptr, true))) return st;
         }
         // step (e): Err from the slice gradients at u^(k+1), phi^(k)
-        if (want_err) {
+        if (ebuf) {
             if ((st = refresh_steps(p))) return st;
             if ((st = slice_pass(p, 0, 0.0, p->grad, true))) return st;
             TimeScope ts(p, KID_ERR);
             ISM_TRY_HIP(launch_err(p->grad, p->s, p->B, p->K, p->N, p->C, p->tau,
-                                   p->path != PATH_GPE, p->Errhist + (size_t)k * p->B, err_rule ? p->active : nullptr,
-                                   err_stop, p->flags, p->stream));
+                                   p->path != PATH_GPE, ebuf + (size_t)k * p->B,
+                                   err_rule ? p->active : nullptr, err_stop, p->flags, p->stream));
         }
         done = k + 1;
     }
@@ -694,15 +728,13 @@ int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, doubl
     if ((st = read_flags(p, fl))) return st;
     if (fl[0] & 2) return ISM_E_UNSUPPORTED;
     if (fl[0]) return ISM_E_NUMERIC;
-    if (J_hist && n_iter > 0) {
-        if ((st = copy_out(p, J_hist, p->Jhist, (size_t)n_iter * p->B * sizeof(double)))) return st;
-    }
-    if (Err_hist && done > 0) {
-        if ((st = copy_out(p, Err_hist, p->Errhist, (size_t)done * p->B * sizeof(double)))) return st;
-    }
-    if (iters_done) *iters_done = done;
+    *done_out = done;
     return ISM_OK;
 }
+
+}  // namespace ism
+
+extern "C" {
 
 int ism_fidelity(ism_problem* p, double* J, double* F) {
     if (!p) return ISM_E_ARG;

@@ -18,6 +18,13 @@ int validate_common(int d, int C, double T, int K, int N, const ism_options* o);
 // per-step data at the current controls without a boundary rebuild (ism_api.cpp)
 int refresh_steps(ism_problem* p);
 
+// the iteration loop of ism_iterate_inner on caller-provided history buffers (ism_api.cpp);
+// `fills` clears flags with launch_fill_i32 instead of host copies and hipMemsetAsync
+int iterate_loop(ism_problem* p, int n_iter, int n_inner, double rho, double fid_stop,
+                 double err_stop, double* jbuf, double* ebuf, bool fills, int* done_out);
+// x[0..n) = v by a kernel (ism_static.hip)
+hipError_t launch_fill_i32(int* x, int v, int n, hipStream_t st);
+
 // serving (ism_api.cpp): enqueue-only iteration steps, no host synchronisation
 int serve_begin(ism_problem* p, double fid_stop);
 int serve_chunk(ism_problem* p, int n, double rho, double fid_stop);
