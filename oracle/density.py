@@ -33,7 +33,8 @@ import numpy as np
 from . import finite as _F
 
 __all__ = ["inner_hs", "forward", "backward", "objective", "gradient", "plain_gradient_method",
-           "assemble", "boundaries", "ism_gradient", "ism_iterate"]
+           "assemble", "boundaries", "ism_gradient", "ism_iterate", "gradient_cn", "objective_cn",
+           "ism_gradient_cn", "plain_gradient_method_cn", "ism_iterate_cn"]
 
 
 def inner_hs(a: np.ndarray, b: np.ndarray) -> complex:
@@ -145,6 +146,93 @@ def ism_iterate(H0, Hc, rho0, target, u0, T, alpha, rho, iters, N):
     Js, Fs = [], []
     for _ in range(iters):
         g, J, F, *_ = ism_gradient(H0, Hc, rho0, target, u, T, alpha, N)
+        Js.append(J); Fs.append(F)
+        u = u + rho * g
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs)}
+
+
+# ----------------------------------------------------------------------------
+# Crank-Nicolson step map on the density matrix (Sec. 3 applied to the conjugation form):
+# rho_{j+1} = U_j rho_j U_j^dagger with U_j = (I + L_j)^{-1} (I - L_j), L_j = (i tau/2) H_j,
+# the Hilbert-space Cayley step of the paper's finite-dimensional scheme.
+# ----------------------------------------------------------------------------
+
+def _cn_step_grad(H, Hc, tau, rho_j, lam_j):
+    """(1/tau) dJ/du_{j,c} of one Crank-Nicolson conjugation step, without the penalty:
+        g_{j,c} = 2 Im Tr( lambda_j (I - L_j)^{-1} H_c (I + L_j)^{-1} rho_j ).
+    From dU/du_c = -(i tau/2) (I+L)^{-1} H_c (I + U): dJ = 2 Re Tr(lambda_{j+1} dU rho_j U^+),
+    U^+ lambda_{j+1} = lambda_j U^+, U^+ (I+L)^{-1} = (I-L)^{-1} and I + U = 2 (I+L)^{-1}."""
+    L = _F.cn_generator(H, tau)
+    I = np.eye(L.shape[0], dtype=np.complex128)
+    a = np.linalg.solve(I + L, rho_j)                     # (I + L)^{-1} rho_j
+    b = np.linalg.solve((I - L).conj().T, lam_j.conj().T).conj().T   # lambda_j (I - L)^{-1}
+    return np.array([2.0 * np.trace(b @ Hc[c] @ a).imag for c in range(Hc.shape[0])])
+
+
+def gradient_cn(H0, Hc, rho0, target, u, T, alpha):
+    """Exact (1/tau) dJ_tau/du of the Crank-Nicolson conjugation map, with J and F at u."""
+    K = u.shape[0]
+    tau = T / K
+    Us = _F.step_unitaries_cn(H0, Hc, u, tau)
+    rho = forward(Us, rho0)
+    lam = backward(Us, target)
+    g = np.zeros_like(u)
+    for j in range(K):
+        H = _F.hamiltonian(H0, Hc, u[j])
+        g[j] = _cn_step_grad(H, Hc, tau, rho[j], lam[j]) - alpha[j] * u[j]
+    J, F = objective(rho[-1], rho0, target, u, alpha, tau)
+    return g, J, F, rho[-1]
+
+
+def objective_cn(H0, Hc, rho0, target, u, T, alpha):
+    """J_tau and F of the Crank-Nicolson conjugation map at u."""
+    K = u.shape[0]
+    rhoK = forward(_F.step_unitaries_cn(H0, Hc, u, T / K), rho0)[-1]
+    return objective(rhoK, rho0, target, u, alpha, T / K)
+
+
+def ism_gradient_cn(H0, Hc, rho0, target, u, T, alpha, N):
+    """ISM gradient (Algorithm 1 steps (a)-(c)) with the Crank-Nicolson conjugation map:
+    slice maps W_n from the Cayley steps, boundaries, intermediate states (Eq. (cible)), and
+    per slice beta_n [ 2 Im Tr(lambda^n_j (I-L_j)^{-1} H_c (I+L_j)^{-1} rho^n_j)
+    - alpha_{n,j} u_{j,c} ].  Returns (g, J, F, phi, Psi, Lam)."""
+    K = u.shape[0]
+    tau = T / K
+    s = _F.slice_starts(K, N)
+    Us = _F.step_unitaries_cn(H0, Hc, u, tau)
+    Psi, Lam = boundaries(assemble(Us, s), rho0, target)
+    phi = _F.intermediate_states(Psi, Lam, s, K)
+    g = np.zeros_like(u)
+    for n in range(N):
+        sn, sn1 = s[n], s[n + 1]
+        beta = K / (sn1 - sn)
+        rho = forward(Us[sn:sn1], phi[n])
+        lam = backward(Us[sn:sn1], phi[n + 1])
+        for j in range(sn, sn1):
+            H = _F.hamiltonian(H0, Hc, u[j])
+            gj = _cn_step_grad(H, Hc, tau, rho[j - sn], lam[j - sn])
+            g[j] = beta * (gj - (alpha[j] / beta) * u[j])
+    J, F = objective(Psi[-1], rho0, target, u, alpha, tau)
+    return g, J, F, phi, Psi, Lam
+
+
+def plain_gradient_method_cn(H0, Hc, rho0, target, u0, T, alpha, rho, iters):
+    """Constant-step gradient ascent (Eq. (gradStep)) with the Crank-Nicolson map."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    Js, Fs = [], []
+    for _ in range(iters):
+        g, J, F, _ = gradient_cn(H0, Hc, rho0, target, u, T, alpha)
+        Js.append(J); Fs.append(F)
+        u = u + rho * g
+    return {"u": u, "J": np.array(Js), "F": np.array(Fs)}
+
+
+def ism_iterate_cn(H0, Hc, rho0, target, u0, T, alpha, rho, iters, N):
+    """ISM with one constant-step gradient step per slice (Algorithm 1), Crank-Nicolson map."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    Js, Fs = [], []
+    for _ in range(iters):
+        g, J, F, *_ = ism_gradient_cn(H0, Hc, rho0, target, u, T, alpha, N)
         Js.append(J); Fs.append(F)
         u = u + rho * g
     return {"u": u, "J": np.array(Js), "F": np.array(Fs)}

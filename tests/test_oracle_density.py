@@ -107,3 +107,77 @@ def test_purity_conserved_and_hermitian():
     for r in (rho[0], rho[13], rho[-1]):
         assert abs(np.trace(r @ r).real - np.trace(p.psi0 @ p.psi0).real) <= 1e-12
         assert np.max(np.abs(r - r.conj().T)) <= 1e-13
+
+
+# --- Crank-Nicolson conjugation map (Sec. 3 Cayley step applied as rho <- U rho U^+) ------
+
+def _J_cn_direct(H0, Hc, R0, Rf, u, T, al):
+    """J_tau of the Cayley conjugation map, each step solved directly with numpy's dense
+    solver on the inputs (no oracle routine)."""
+    K = u.shape[0]
+    tau = T / K
+    d = H0.shape[0]
+    I = np.eye(d)
+    rho = R0.astype(complex)
+    for j in range(K):
+        H = H0 + sum(u[j, c] * Hc[c] for c in range(Hc.shape[0]))
+        U = np.linalg.solve(I + 0.5j * tau * H, I - 0.5j * tau * H)
+        rho = U @ rho @ U.conj().T
+    return float(np.vdot(Rf, rho).real) - 0.5 * tau * float(np.sum(al[:, None] * u ** 2))
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.25])
+def test_cn_gradient_fd(alpha):
+    """tau g of the Crank-Nicolson conjugation map against central finite differences of J
+    computed by direct dense solves (rel 1e-8)."""
+    H0, Hc, R0, Rf, u, T = _tiny(seed=44, K=12, T=1.1)
+    al = np.full(12, alpha)
+    g, J, *_ = D.gradient_cn(H0, Hc, R0, Rf, u, T, al)
+    assert abs(J - _J_cn_direct(H0, Hc, R0, Rf, u, T, al)) <= 1e-12
+    tau, eps = T / 12, 1e-6
+    fd = np.zeros_like(u)
+    for j in range(12):
+        for c in range(Hc.shape[0]):
+            up, um = u.copy(), u.copy()
+            up[j, c] += eps
+            um[j, c] -= eps
+            fd[j, c] = (_J_cn_direct(H0, Hc, R0, Rf, up, T, al) -
+                        _J_cn_direct(H0, Hc, R0, Rf, um, T, al)) / (2 * eps)
+    assert np.linalg.norm(tau * g - fd) / np.linalg.norm(fd) <= 1e-8
+
+
+def test_cn_gradient_is_not_the_exponential_one():
+    """Guard: the exponential map's gradient evaluated on the same controls misses the
+    Crank-Nicolson finite differences at this step size, so the pin above tells them apart."""
+    H0, Hc, R0, Rf, u, T = _tiny(seed=44, K=12, T=1.1)
+    al = np.zeros(12)
+    g_exp, *_ = D.gradient(H0, Hc, R0, Rf, u, T, al)
+    g_cn, *_ = D.gradient_cn(H0, Hc, R0, Rf, u, T, al)
+    assert np.linalg.norm(g_exp - g_cn) / np.linalg.norm(g_cn) > 1e-3
+
+
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_cn_ism_equals_plain(N):
+    """Theorem 2 with the Cayley conjugation map: the ISM slice gradients (non-divisible K
+    included) equal the plain gradient per call, and the iterates over several steps."""
+    H0, Hc, R0, Rf, u, T = _tiny(seed=45, K=17, T=0.8)
+    al = np.full(17, 0.1)
+    g, J, F, _ = D.gradient_cn(H0, Hc, R0, Rf, u, T, al)
+    gi, Ji, Fi, *_ = D.ism_gradient_cn(H0, Hc, R0, Rf, u, T, al, N)
+    assert np.max(np.abs(gi - g)) <= 1e-12 * max(1.0, np.max(np.abs(g)))
+    assert abs(Ji - J) <= 1e-13 and abs(Fi - F) <= 1e-13
+    a = D.plain_gradient_method_cn(H0, Hc, R0, Rf, u, T, al, 0.05, 6)
+    b = D.ism_iterate_cn(H0, Hc, R0, Rf, u, T, al, 0.05, 6, N)
+    assert np.max(np.abs(a["u"] - b["u"])) <= 1e-10
+    assert np.max(np.abs(a["J"] - b["J"])) <= 1e-10
+
+
+def test_cn_conjugation_preserves_purity():
+    """Each Cayley step is unitary, so Tr(rho^2) and hermiticity are conserved."""
+    H0, Hc, R0, Rf, u, T = _tiny(seed=46, K=40, T=2.0)
+    Us = O.step_unitaries_cn(H0, Hc, u, T / 40)
+    rho = D.forward(Us, R0)
+    p0 = np.trace(R0 @ R0).real
+    for r in rho:
+        assert abs(np.trace(r @ r).real - p0) <= 1e-12 * p0
+        assert np.max(np.abs(r - r.conj().T)) <= 1e-12
