@@ -105,3 +105,28 @@ def gpe_psi_end(p, K: int) -> np.ndarray:
         th = tau * (V + LD(p.g) * (a.real ** 2 + a.imag ** 2))
         psi = sf.ifft(half * sf.fft(np.exp(-1j * th) * a))
     return psi.astype(np.complex128)
+
+
+def density_cn_end(p, K: int) -> np.ndarray:
+    """rho_K of the Crank-Nicolson conjugation map over the first K steps of p's controls
+    (instance 0): rho <- U rho U^dagger with U - I = 2 sum_{k>=1} (-L)^k, L = (i tau/2) H_j,
+    the series summed to 11 terms (tau ||H|| / 2 ~ 1.5e-3 on the five-spin run, so the
+    remainder is below 1e-30), every operation in extended precision (tau = T/K of p)."""
+    H0 = np.asarray(p.H0).astype(CLD)
+    Hc = np.asarray(p.Hc).astype(CLD)
+    tau = LD(p.T) / LD(p.K)
+    u = p.u0[0, :K].astype(LD)
+    rho = np.asarray(p.psi0).astype(CLD)
+    for j in range(K):
+        H = H0.copy()
+        for c in range(Hc.shape[0]):
+            H = H + u[j, c] * Hc[c]
+        L = (0.5j * tau) * H
+        term = -L
+        D = 2 * term
+        for _ in range(10):
+            term = -(term @ L)
+            D = D + 2 * term
+        Dh = D.conj().T
+        rho = rho + (D @ rho + rho @ Dh) + D @ rho @ Dh
+    return rho.astype(np.complex128)

@@ -66,6 +66,28 @@ def test_cn_map_over_20000_steps():
         assert np.linalg.norm(lam0 - xb[i]) <= 5e-13, np.linalg.norm(lam0 - xb[i])
 
 
+def test_density_cn_map_over_1024_steps():
+    """The five-spin density run (d = 32, tau = T/2^15) under the Crank-Nicolson map: the
+    oracle's conjugation by U_j = I + D_j, D_j = -2 (I + L_j)^{-1} L_j, against the
+    extended-precision evaluation over the first 1024 steps (measured 1.8e-15); and the guard:
+    conjugating by the rounded U_j = (I + L_j)^{-1}(I - L_j) itself, whose entries near 1
+    carry a rounding that repeats from step to step, drifts much further (6.4e-14 here,
+    1.8e-12 at the full 2^15 steps)."""
+    from oracle import density as D
+    p = problems.spin5_density()
+    Kc = 1024
+    tau = p.T / p.K
+    ref = X.density_cn_end(p, Kc)
+    n0 = np.linalg.norm(p.psi0)
+    Ds = [D._cn_difference(O.hamiltonian(p.H0, p.Hc, p.u0[0, j]), tau) for j in range(Kc)]
+    got = D.forward_cn(Ds, p.psi0)[-1]
+    err = np.linalg.norm(got - ref) / n0
+    assert err <= 5e-15, err
+    Us = [O.step_unitary_cn(O.hamiltonian(p.H0, p.Hc, p.u0[0, j]), tau) for j in range(Kc)]
+    guard = np.linalg.norm(D.forward(Us, p.psi0)[-1] - ref) / n0
+    assert guard > 3e-14, guard
+
+
 def test_extended_reference_closed_forms():
     """The reference itself: with u = 0 every basis component only turns its phase,
     psi_r(T) = e^{-i B r(r+1) T} (P14), and the Crank-Nicolson phase is that of the Cayley
