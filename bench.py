@@ -72,16 +72,20 @@ def copy_calibration():
                                            "write_bytes": COPY_BYTES, "launches": 3}}), flush=True)
 
 
-def serving_sample(n_req, iters_per_round=5, max_running=16):
+def serving_sample(n_req, max_iter=20, iters_per_round=5, max_running=16):
     """Replay of the first n_req requests of the seeded 200 req/s serving trace at their
-    arrival times (FP32 mixed; stop at F >= 0.99 or 200 iterations)."""
+    arrival times (FP32 mixed; stop at F >= 0.99 or max_iter iterations).  The trace offers
+    far more work than the device serves (200 requests arrive within about a second), so the
+    server is saturated from the start and solves/s over the replay is its sustainable rate
+    for this request mix."""
+    import numpy as np
     import problems
     from paper_1603_01237_amd import Server
     from paper_1603_01237_amd.serve import latency_summary, replay
     trace = problems.serving_trace()[:n_req]
     types = [f"{r['type']}{r['size']}" for r in trace]
     items = [(r["arrival"] - trace[0]["arrival"], problems.request_problem(r),
-              dict(max_iter=200, rho=problems.SERVE_RHO[r["type"]], fid_stop=0.99,
+              dict(max_iter=max_iter, rho=problems.SERVE_RHO[r["type"]], fid_stop=0.99,
                    precision="fp32")) for r in trace]
     with Server(200 << 30, iters_per_round=iters_per_round, max_running=max_running) as s:
         recs, wall = replay(s, items, timeout=600.0, report_every=10.0,
@@ -90,16 +94,22 @@ def serving_sample(n_req, iters_per_round=5, max_running=16):
     out = latency_summary(recs, wall)
     by_type = {}
     for t, r in zip(types, recs):
-        by_type.setdefault(t, []).append(round(r["latency_s"], 3))
-    out["latency_s_by_type"] = by_type
-    out.update({"busy_frac": st["busy_s"] / wall if wall > 0 else None,
+        by_type.setdefault(t, []).append(r["latency_s"])
+    out["latency_s_by_type"] = {t: {"n": len(v), "p50": float(np.percentile(v, 50)),
+                                    "p99": float(np.percentile(v, 99))}
+                                for t, v in sorted(by_type.items())}
+    out.update({"sustainable_solves_per_s": out["solves_per_s"],
+                "offered_req_per_s": n_req / max(trace[-1]["arrival"] - trace[0]["arrival"], 1e-9),
+                "handles": st["groups"], "merged_requests": st["merged"],
+                "busy_frac": st["busy_s"] / wall if wall > 0 else None,
                 "peak_device_GB": st["bytes_peak"] / 1e9,
                 "mean_iters": float(sum(r["iters"] for r in recs) / max(len(recs), 1)),
                 "reached_F099": int(sum(r["F"] >= 0.99 for r in recs)),
                 "sample": f"first {n_req} requests of the seeded 200 req/s trace (spin d in "
                           "{4,16,64,256}, rotor j<=10/20/40, GPE n=1024/4096; K log-uniform "
                           "1000..20000, N 16..128), arrival-time replay, FP32 mixed, stop at "
-                          "F>=0.99 or 200 iterations"})
+                          f"F>=0.99 or {max_iter} iterations (the trace's 200 capped to keep the "
+                          "replay near a minute); busy_frac: time with a request running"})
     return out
 
 
@@ -149,6 +159,45 @@ def gate_gemm_flops(prob, d):
     return 8.0 * d ** 3 * (3 * K - 2 * N + extra)
 
 
+def gate_grad_flops(prob, prec):
+    """Algorithmic work of one launch of the dense path's gradient kernel, summed over the K
+    steps with the Krylov order m_j each step needs at its controls (the kernel's own rule:
+    x = 2 tau (||H0 - s||_inf + sum_c |u_jc| ||H_c||_inf), terms until x^(m+2)/(m+3)! is
+    below 1e-17 in FP64, min(1e-8, 1e-5/K) in FP32).  Per step and column of X_j, Y_j and per
+    row r with w_r entries in the union pattern of H0 and the controls:
+      16 m w_r        the Krylov sequences p_a = (tau H')^a y and r_b = (tau H')^b x
+      2 (m+1)(m+2)    the weights t_b = sum_a conj(w_ab) p_a (real weight times complex)
+      8 (m+1) w_r     S_w = sum_b conj(t_b) r_b(col_w)
+      4 nnz_c(r)      Im(h S_w) per control entry of the row (summed over controls)."""
+    import numpy as np
+    K, d, C = prob.K, prob.d, prob.C
+    H0 = prob.H0_of(0)
+    dg = np.real(np.diag(H0))
+    s = 0.5 * (dg.max() + dg.min())
+    pat = np.abs(H0) > 0
+    np.fill_diagonal(pat, True)
+    nnz_c = 0
+    for c in range(C):
+        pat |= np.abs(prob.Hc[c]) > 0
+        nnz_c += int((np.abs(prob.Hc[c]) > 0).sum())
+    w_sum = float(pat.sum())
+    h0norm = float(np.abs(H0 - s * np.eye(d)).sum(axis=1).max())
+    cnorm = np.array([np.abs(prob.Hc[c]).sum(axis=1).max() for c in range(C)])
+    tau = prob.T / K
+    tol = 1e-17 if prec == "fp64" else min(1e-8, 1e-5 / K)
+    cap = 16 if prec == "fp64" else 12
+    u = prob.u0[0]
+    total = 0.0
+    for j in range(K):
+        x = 2 * tau * (h0norm + float(np.abs(u[j]) @ cnorm))
+        m, rem = 1, x * x / 6
+        while m < cap and rem > tol:
+            m += 1
+            rem = rem * x / (m + 2)
+        total += d * (16 * m * w_sum + d * 2 * (m + 1) * (m + 2) + 8 * (m + 1) * w_sum + 4 * nnz_c)
+    return total
+
+
 def gpe_sweep_flops(prob):
     """FFT work of the two sequential sweeps of one iteration: 2K steps of two length-n
     transforms at 5 n log2 n flops each (pointwise work not counted)."""
@@ -169,6 +218,7 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2,
         out.update(_rotor_inner_workload(stream))
     if "density" in which:
         out.update(_density_workload(stream))
+        out.update(_density_cn_workload(stream))
     if "spins" in which:
         out.update(_spins_workload(stream))
     if "gate" in which:
@@ -268,6 +318,23 @@ def _density_workload(stream, steps=2):
     return {"spin5_density": out}
 
 
+def _density_cn_workload(stream, steps=2):
+    """The five-spin density-matrix run with the Crank-Nicolson map at tau = T / 2^15, N = 8
+    (Sec. 3 scheme on the conjugation form): Cayley steps built as D_j = U_j - I by a Neumann
+    series, the gradient from A x and A y, A = (I + L_j)^{-1}."""
+    import problems
+    p = problems.spin5_density()
+    r = {prec: run_gpu(prec, p, steps, 1, stream, step_map="cn") for prec in ("fp32", "fp64")}
+    return {"spin5_density_cn": {
+        "workload": f"five spins, density matrices (d=32), Crank-Nicolson map, K={p.K} "
+                    f"(tau = T/2^15), N={p.N}, one ISM iteration per step",
+        "ms_per_iteration": {k: v["seconds"] / steps * 1e3 for k, v in r.items()},
+        "useful_matrix_steps_per_s": {k: 2 * p.K * steps / v["seconds"] for k, v in r.items()},
+        "kernels_ms_per_iteration": {k: {n: t[1] / steps for n, t in v["kernels"].items()}
+                                     for k, v in r.items()},
+        "final_J": {k: v["J_mean"] for k, v in r.items()}}}
+
+
 def _spins_workload(stream):
     import problems
     out = {}
@@ -299,6 +366,15 @@ def _gate_workload(stream, iters_gate):
         ent[f"roofline_{prec}"] = {"bound": "mfma", "kernel": "gate_gemm (all batched GEMMs)",
                                    "achieved": ach / 1e12, "peak": PEAK_MFMA[prec] / 1e12,
                                    "unit": "TFLOP/s", "frac": ach / PEAK_MFMA[prec]}
+        # the gradient kernel: one effective launch per iteration (of the two Krylov bounds,
+        # the one not needed exits at once); controls at u0 (the timed iterations move them
+        # little, and m_j is recomputed at u0 here)
+        launches, ms = v["kernels"]["gate_grad"]
+        ach = gate_grad_flops(pg, prec) * iters_gate / (ms * 1e-3)
+        ent[f"roofline_grad_{prec}"] = {"bound": "alu", "kernel": "gate_grad",
+                                        "achieved": ach / 1e12, "peak": PEAK_ALU / 1e12,
+                                        "unit": "TFLOP/s", "frac": ach / PEAK_ALU,
+                                        "algorithmic_TFLOP_per_launch": gate_grad_flops(pg, prec) / 1e12}
     out["gate_d256"] = ent
     return out
 
@@ -353,8 +429,11 @@ def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp", 
     h.set_timing(False)
     info = h.info()
     if info["path"] == 0:
-        m_b, S_b = h.taylor_params()
-        info["terms"] = [m * S for m, S in zip(m_b, S_b)]
+        try:
+            m_b, S_b = h.taylor_params()
+            info["terms"] = [m * S for m, S in zip(m_b, S_b)]
+        except _lib.IsmError:     # one-launch solve: its series are chosen per step
+            info["terms"] = None
     J, F = h.fidelity()
     h.close()
     out = {"seconds": t1 - t0, "kernels": kt, "info": info, "J_mean": float(J.mean()),
@@ -364,21 +443,152 @@ def run_gpu(prec, prob, steps, warmup, stream_ptr, timing=True, step_map="exp", 
     return out
 
 
-def cpu_baseline(prob, n_inst):
-    """The FP64 oracle's ISM iteration (Algorithm 1, one gradient step per slice) on a
-    bounded sample of instances of the same workload, single thread."""
+def _cpu_info():
+    """CPU model, logical CPUs and physical cores of this host (Linux /proc/cpuinfo)."""
+    model, cores = "unknown", set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model == "unknown":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(), "physical_cores": len(cores) or None}
+
+
+def _slice_worker(conn, H0, Hc, psi0, target, T, K, N, alpha, mine):
+    """One process of the CPU-parallel ISM (the paper's one-process-per-slice layout, several
+    slices per process): for its slices, the step propagators, step averages and slice
+    propagator (Sec. 3, propagator assembling), then the slice gradients once the master has
+    sent the intermediate states."""
     from threadpoolctl import threadpool_limits
     from oracle import finite as O
-    t0 = time.perf_counter()
+    s = O.slice_starts(K, N)
+    tau = T / K
     with threadpool_limits(1):
-        for b in range(n_inst):
-            g, J, F, *_ = O.ism_gradient(prob.H0[b], prob.Hc, prob.psi0, prob.target, prob.u0[b],
-                                         prob.T, prob.alpha, prob.N)
-            _ = prob.u0[b] + prob.rho * g
-    dt = time.perf_counter() - t0
-    return {"value": n_inst * 2 * prob.K / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_inst} of {prob.batch} instances x 1 ISM iteration (K={prob.K}, "
-                      f"N={prob.N}), FP64 NumPy, one thread; {dt:.1f} s"}
+        while True:
+            msg = conn.recv()
+            if msg is None:
+                return
+            if msg[0] == "build":
+                u = msg[1]
+                Us, Hh, Ms = {}, {}, {}
+                for n in mine:
+                    for j in range(s[n], s[n + 1]):
+                        Us[j] = O.step_unitary(O.hamiltonian(H0, Hc, u[j]), tau)
+                        Hh[j] = O.hhat(O.hamiltonian(H0, Hc, u[j]), Hc, tau)
+                    Ms[n] = O.assemble([Us[j] for j in range(s[n], s[n + 1])], [0, s[n + 1] - s[n]])[0]
+                conn.send(Ms)
+            else:
+                phi = msg[1]
+                out = {}
+                for n in mine:
+                    UU = [None] * K
+                    HH = [None] * K
+                    for j in range(s[n], s[n + 1]):
+                        UU[j], HH[j] = Us[j], Hh[j]
+                    out[n] = O.ism_slice_gradient(UU, HH, u, alpha, phi[n], phi[n + 1], s[n],
+                                                  s[n + 1], K)[0]
+                conn.send(out)
+
+
+def cpu_baseline(prob, n_inst, reps=5, warm=2):
+    """The FP64 oracle timed on this host, on a bounded sample of the workload: one ISM
+    iteration (Algorithm 1, one gradient step per slice) of instance 0, the median of `reps`
+    repetitions after `warm` untimed ones.
+      - single core: the oracle's ISM iteration in one thread;
+      - P cores: the paper's CPU-parallel ISM, P = min(N, physical cores, 16) worker
+        processes holding contiguous blocks of slices, the master doing the boundary rebuild
+        (2N products) and the update."""
+    import multiprocessing as mp
+    import statistics
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import finite as O
+    b = 0
+    H0, u0 = prob.H0_of(b), prob.u0[b]
+
+    def one_core():
+        with threadpool_limits(1):
+            g, *_ = O.ism_gradient(H0, prob.Hc, prob.psi0, prob.target, u0, prob.T, prob.alpha,
+                                   prob.N)
+            return u0 + prob.rho * g
+
+    times = []
+    for k in range(warm + reps):
+        t0 = time.perf_counter()
+        u1 = one_core()
+        if k >= warm:
+            times.append(time.perf_counter() - t0)
+    t1 = statistics.median(times)
+    info = _cpu_info()
+    P = max(1, min(prob.N, info["physical_cores"] or os.cpu_count() or 1, 16))
+    s = O.slice_starts(prob.K, prob.N)
+    blocks = [list(range(w * prob.N // P, (w + 1) * prob.N // P)) for w in range(P)]
+    ctx = mp.get_context("spawn")
+    pipes, procs = [], []
+    for w in range(P):
+        a, c = ctx.Pipe()
+        pr = ctx.Process(target=_slice_worker, args=(c, H0, prob.Hc, prob.psi0, prob.target,
+                                                     prob.T, prob.K, prob.N, prob.alpha,
+                                                     blocks[w]), daemon=True)
+        pr.start()
+        pipes.append(a)
+        procs.append(pr)
+
+    def p_cores():
+        for a in pipes:
+            a.send(("build", u0))
+        Ms = {}
+        for a in pipes:
+            Ms.update(a.recv())
+        Psi, Lam = O.boundaries([Ms[n] for n in range(prob.N)], prob.psi0, prob.target)
+        phi = O.intermediate_states(Psi, Lam, s, prob.K)
+        for a in pipes:
+            a.send(("grad", phi))
+        g = np.zeros_like(u0)
+        for a in pipes:
+            for n, gn in a.recv().items():
+                g[s[n]:s[n + 1]] = gn
+        return u0 + prob.rho * g
+
+    ptimes = []
+    try:
+        for k in range(warm + reps):
+            t0 = time.perf_counter()
+            uP = p_cores()
+            if k >= warm:
+                ptimes.append(time.perf_counter() - t0)
+    finally:
+        for a in pipes:
+            a.send(None)
+        for pr in procs:
+            pr.join(timeout=10)
+    tP = statistics.median(ptimes)
+    same = float(np.max(np.abs(uP - u1)))
+    steps = 2 * prob.K                     # useful steps of one instance and iteration
+    return {"value": steps / t1, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"instance 0 of {prob.batch}, 1 ISM iteration (K={prob.K}, N={prob.N}), "
+                      f"FP64 NumPy, one thread; median of {reps} after {warm} warm-ups: "
+                      f"{t1:.2f} s",
+            "p_cores": {"value": steps / tP, "unit": "steps/s", "cores": P,
+                        "sample": f"same iteration, {P} worker processes with contiguous "
+                                  f"slice blocks, boundaries on the master; median "
+                                  f"{tP:.2f} s; controls equal the single-core ones to "
+                                  f"{same:.1e}"},
+            "host": info}
 
 
 def main():
@@ -391,7 +601,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the two-spin, gate and condensate workloads")
-    ap.add_argument("--serve", type=int, default=16,
+    ap.add_argument("--serve", type=int, default=200,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
     ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn", "rotor_inner", "density"],
                     help="run only this secondary workload and print its figures (profiling)")

@@ -109,6 +109,12 @@ typedef struct ism_options {
                                creating and destroying the handle never synchronises the whole
                                device (default 0: hipMalloc / hipFree) */
     int step_map;           /* ism_step_map of a state problem (default ISM_STEP_EXP) */
+    int launch_per_pass;    /* 0 (default): small FP64 state problems (d <= 4, at most 4
+                               controls and 64 slices, exponential map) run ism_iterate and
+                               their served iterations as one persistent launch, one workgroup
+                               per instance holding every phase of Algorithm 1; 1: always the
+                               sequence of per-pass launches.  Both give the iterates of
+                               Algorithm 1 to FP64 rounding (not bitwise the same). */
 } ism_options;
 
 /* Fill *opt with the defaults listed above.  opt must not be NULL. */
@@ -234,6 +240,29 @@ int ism_iterate_static(ism_problem* p, int n_iter, double rho, double fid_stop, 
 int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, double fid_stop,
                       double err_stop, double* J_hist, double* Err_hist, int* iters_done);
 
+/*
+ * ISM iterations whose Step (c) is one Newton step per slice problem (Sec. 4.B: the
+ * matrix-free Newton method with a GMRES solver, the paper's second slice solver for the
+ * molecular-orientation runs).  Iteration k rebuilds the boundaries and intermediate states
+ * phi^(k) at u^(k) (steps (a)-(b)); then every slice n solves
+ *     A_n delta_n = -G_n,   G_n = beta_n grad J_n[u_n, phi^(k)],
+ * A_n the Jacobian of G_n applied matrix-free as (G_n(u + eps v) - G_n(u - eps v)) / (2 eps),
+ * by gmres_m steps of GMRES from delta_n = 0 (Euclidean inner product over the slice's
+ * controls, modified Gram-Schmidt, no restart; a breakdown, h_{i+1,i} <= 1e-14 ||A v_i||,
+ * ends that slice's Arnoldi early), and takes the full step u_n <- u_n + delta_n (no damping).
+ * One Newton step costs 2 gmres_m + 1 slice passes.
+ *   gmres_m   1 <= gmres_m <= 32 (else ISM_E_ARG).
+ *   fd_eps    > 0, the difference step along unit vectors (1e-5 suits O(1) controls).
+ *   fid_stop, J_hist, iters_done: as ism_iterate (J_hist rows past *iters_done + 1 are not
+ *             written).
+ * FP64 handles of the state, gate and density paths only (ISM_E_UNSUPPORTED otherwise: the
+ * difference quotient needs FP64 gradients).  Device memory: (gmres_m + 6) B K C doubles and
+ * B N (gmres_m + 2)^2 doubles, allocated on the first call with a larger gmres_m and held
+ * by the handle.  ISM_E_NUMERIC if J becomes NaN/Inf.
+ */
+int ism_iterate_newton(ism_problem* p, int n_iter, int gmres_m, double fd_eps, double fid_stop,
+                       double* J_hist, int* iters_done);
+
 /* J = Re<psi(T)|psi_f> - tau/2 sum_j alpha_j |u_j|^2 and F = |<psi(T)|psi_f>|^2 per instance
  * (gate: Re Tr(W^+ U)/d and |Tr(W^+ U)|^2/d^2), B doubles each (either may be NULL).
  * Recomputes the boundaries if the controls changed since the last forward pass. */
@@ -254,8 +283,9 @@ int ism_problem_info(const ism_problem* p, ism_info* info);
 /* Sparse path: the series parameters of every instance at the last forward pass, Taylor
  * terms m[b] and sub-steps S[b] per step (exponential map) or Neumann terms m[b] and S[b] = 1
  * (Crank-Nicolson), b < batch; host arrays of batch ints, written after a synchronisation
- * of the handle's stream.  ISM_E_STATE before the first forward pass, ISM_E_UNSUPPORTED on
- * the dense and Gross-Pitaevskii paths. */
+ * of the handle's stream.  ISM_E_STATE before the first forward pass and on handles whose
+ * boundaries come from the one-launch solve of small problems (which picks its series per
+ * step; see launch_per_pass), ISM_E_UNSUPPORTED on the dense and Gross-Pitaevskii paths. */
 int ism_taylor_params(const ism_problem* p, int* m, int* S);
 
 /*
@@ -290,15 +320,21 @@ size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kin
  * (ism_iterate semantics, u <- u + rho g) until F = |<psi(T)|psi_f>|^2 >= fid_stop or
  * max_iter updates.  The server copies every input at submit time.  Requests are
  * admitted in arrival order while the device memory they would hold
- * (ism_problem_footprint, or the handle's actual bytes if larger) fits in hbm_budget;
- * each admitted request gets its own handle and HIP stream, so the kernels of different
- * requests overlap on the device.  Work is issued in chunks of iters_per_round
- * iterations with no host synchronisation; ism_server_progress polls the chunks' events,
- * retires finished requests (freeing their memory), admits waiting ones and issues the
- * next chunks.  It never blocks on device work, except inside handle creation and when
- * a finished request's controls are copied out.  A request's result does not depend on
- * what else is being served: its kernels and their launch shapes are those of a solve
- * run alone.
+ * (ism_problem_footprint, or the handle's actual bytes if larger) fits in hbm_budget.
+ * The head of the queue is admitted together with every queued request that differs from
+ * it only in the diagonal of H0 (finite state problems with the same d, controls, psi0,
+ * target, off-diagonal H0, T, K, N, precision, rho, fid_stop and max_iter; at most 256):
+ * they run as the instances of one batched handle, so one set of launches serves them all,
+ * and each instance freezes on its own.  Each such group has its own handle and HIP stream,
+ * so the kernels of different groups overlap on the device.  Work is issued in chunks of
+ * iters_per_round iterations with no host synchronisation; ism_server_progress polls the
+ * chunks' events, finishes requests (copying their controls out), retires finished groups
+ * (freeing their memory), admits waiting ones and issues the next chunks.  It never blocks
+ * on device work, except inside handle creation and when a finished request's controls are
+ * copied out.  A request's result does not depend on what else is being served: the
+ * kernels compute every instance of a batch independently, with the arithmetic of its lone
+ * run, so a merged request returns bitwise what it would alone.  An error inside a group
+ * (a non-finite value, a device failure) fails all its running requests.
  *
  * A server is not thread-safe.  Time stamps are seconds on a monotonic clock
  * (ism_server_clock).
@@ -354,9 +390,11 @@ typedef struct ism_result {
 
 typedef struct ism_server_stats {
     uint64_t submitted, completed, failed;
-    int queued, running;
+    int queued, running;    /* requests waiting / admitted and not finished */
     size_t bytes_in_use, bytes_peak;
     double busy_s;          /* time with at least one request running */
+    uint64_t groups;        /* handles admitted so far (one per group of merged requests) */
+    uint64_t merged;        /* requests admitted into another request's handle */
 } ism_server_stats;
 
 /* Monotonic clock in seconds, the time base of all server time stamps. */

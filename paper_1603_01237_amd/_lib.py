@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32_MIXED, "fp32_mixed": FP32_MIXED}
 EXPORTED = [
     "ism_default_options", "ism_problem_create", "ism_problem_create_gpe", "ism_problem_destroy",
     "ism_set_controls", "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient",
-    "ism_iterate", "ism_iterate_inner", "ism_iterate_static", "ism_fidelity", "ism_problem_info", "ism_taylor_params", "ism_status_string", "ism_problem_footprint",
+    "ism_iterate", "ism_iterate_inner", "ism_iterate_static", "ism_iterate_newton", "ism_fidelity", "ism_problem_info", "ism_taylor_params", "ism_status_string", "ism_problem_footprint",
     "ism_set_timing", "ism_kernel_times",
     "ism_server_clock", "ism_server_create", "ism_server_submit", "ism_server_progress",
     "ism_server_poll", "ism_server_take", "ism_server_stats_get", "ism_server_destroy",
@@ -45,7 +45,8 @@ class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("kind", ct.c_int), ("batch", ct.c_int),
                 ("h0_batched", ct.c_int), ("alpha", ct.POINTER(ct.c_double)),
                 ("alpha_len", ct.c_int), ("device", ct.c_int), ("stream", ct.c_void_p),
-                ("io_device", ct.c_int), ("alloc_async", ct.c_int), ("step_map", ct.c_int)]
+                ("io_device", ct.c_int), ("alloc_async", ct.c_int), ("step_map", ct.c_int),
+                ("launch_per_pass", ct.c_int)]
 
 
 class Info(ct.Structure):
@@ -78,7 +79,8 @@ class Result(ct.Structure):
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_uint64), ("completed", ct.c_uint64), ("failed", ct.c_uint64),
                 ("queued", ct.c_int), ("running", ct.c_int), ("bytes_in_use", ct.c_size_t),
-                ("bytes_peak", ct.c_size_t), ("busy_s", ct.c_double)]
+                ("bytes_peak", ct.c_size_t), ("busy_s", ct.c_double), ("groups", ct.c_uint64),
+                ("merged", ct.c_uint64)]
 
 
 _lib = None
@@ -118,6 +120,8 @@ def lib():
                                      ct.POINTER(ct.c_int)]
     L.ism_iterate_inner.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_double,
                                     vp, vp, ct.POINTER(ct.c_int)]
+    L.ism_iterate_newton.argtypes = [vp, ct.c_int, ct.c_int, ct.c_double, ct.c_double, vp,
+                                     ct.POINTER(ct.c_int)]
     L.ism_fidelity.argtypes = [vp, vp, vp]
     L.ism_problem_info.argtypes = [vp, ct.POINTER(Info)]
     L.ism_taylor_params.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
@@ -146,7 +150,8 @@ def lib():
         getattr(L, name).restype = ct.c_int
     for name in ("ism_problem_create", "ism_problem_create_gpe", "ism_set_controls",
                  "ism_get_controls", "ism_forward", "ism_adjoint", "ism_gradient", "ism_iterate",
-                 "ism_iterate_inner", "ism_iterate_static", "ism_fidelity", "ism_problem_info"):
+                 "ism_iterate_inner", "ism_iterate_static", "ism_iterate_newton", "ism_fidelity",
+                 "ism_problem_info"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -172,6 +177,22 @@ def _as_c128(x, shape=None) -> np.ndarray:
     return a
 
 
+def _handle_stream(stream, io_device, device):
+    """(torch stream, raw stream pointer) for a new handle.  A handle exchanging device
+    tensors gets a stream torch knows, so that callers (the autograd wrapper) can order it
+    against torch's current stream: the caller's stream pointer wrapped as an external
+    stream, or a new torch stream of default priority.  Host-I/O handles keep the caller's
+    pointer, or NULL for a library-owned stream."""
+    if not io_device:
+        return None, stream
+    import torch
+    if stream is None:
+        ts = torch.cuda.Stream(device=device)
+    else:
+        ts = torch.cuda.ExternalStream(int(stream), device=device)
+    return ts, ts.cuda_stream
+
+
 def footprint(d, n_ctrl, K, N, batch=1, kind=STATE, precision=FP64, gpe_grid=0) -> int:
     return int(lib().ism_problem_footprint(d, n_ctrl, K, N, batch, kind, precision, gpe_grid))
 
@@ -189,12 +210,13 @@ class Problem:
         self.io_device = io_device
         self.gpe_n = gpe_n
         self.version = 0          # incremented whenever the controls are set
+        self.torch_stream = None  # the handle's stream as a torch stream (io_device handles)
 
     # ------------------------------------------------------------------ creation
     @classmethod
     def create(cls, H0, Hc, psi0, target, T, K, N, precision="fp64", kind="state", batch=1,
                h0_batched=False, alpha=None, device=0, stream=None, io_device=False,
-               step_map="exp"):
+               step_map="exp", launch_per_pass=False):
         L = lib()
         Hc = _as_c128(Hc)
         C, d = Hc.shape[0], Hc.shape[-1]
@@ -217,14 +239,18 @@ class Problem:
             o.alpha = al.ctypes.data_as(ct.POINTER(ct.c_double))
             o.alpha_len = al.shape[0]
         o.device = int(device)
+        tstream, stream = _handle_stream(stream, io_device, device)
         o.stream = stream
         o.io_device = 1 if io_device else 0
         o.step_map = STEP_MAPS[step_map] if isinstance(step_map, str) else int(step_map)
+        o.launch_per_pass = 1 if launch_per_pass else 0
         h = ct.c_void_p()
         _check(L.ism_problem_create(ct.byref(h), d, C, _cptr(H0), _cptr(Hc), _cptr(psi0),
                                     _cptr(target), float(T), int(K), int(N), ct.byref(o)),
                "ism_problem_create")
-        return cls(h, sshape, d, C, int(K), int(N), int(batch), io_device, T=T)
+        obj = cls(h, sshape, d, C, int(K), int(N), int(batch), io_device, T=T)
+        obj.torch_stream = tstream
+        return obj
 
     @classmethod
     def create_gpe(cls, n, L_box, g, V0, V1, V2, psi0, target, T, K, N, precision="fp64",
@@ -239,6 +265,7 @@ class Problem:
         o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         o.batch = int(batch)
         o.device = int(device)
+        tstream, stream = _handle_stream(stream, io_device, device)
         o.stream = stream
         o.io_device = 1 if io_device else 0
         h = ct.c_void_p()
@@ -246,7 +273,9 @@ class Problem:
                                         _cptr(V1), float(V2), _cptr(psi0), _cptr(target),
                                         float(T), int(K), int(N), ct.byref(o)),
                "ism_problem_create_gpe")
-        return cls(h, (n,), n, 1, int(K), int(N), int(batch), io_device, gpe_n=n, T=T)
+        obj = cls(h, (n,), n, 1, int(K), int(N), int(batch), io_device, gpe_n=n, T=T)
+        obj.torch_stream = tstream
+        return obj
 
     # ------------------------------------------------------------------ lifetime
     def close(self):
@@ -356,6 +385,20 @@ class Problem:
             Eh = Eh[:done.value]
         return Jh, Eh, done.value
 
+    def iterate_newton(self, n_iter, gmres_m, fd_eps=1e-5, fid_stop=2.0, record=True):
+        """ism_iterate_newton: returns (J history [rows, B], iters_done), rows =
+        min(n_iter, iters_done + 1), the rows the call wrote."""
+        Jh = self._out((max(n_iter, 1), self.B), np.float64) if record else None
+        done = ct.c_int(0)
+        _check(lib().ism_iterate_newton(self._h, int(n_iter), int(gmres_m), float(fd_eps),
+                                        float(fid_stop),
+                                        self._ptr(Jh) if Jh is not None else None,
+                                        ct.byref(done)),
+               "ism_iterate_newton")
+        if Jh is not None:
+            Jh = Jh[:min(n_iter, done.value + 1)]
+        return Jh, done.value
+
     def fidelity(self):
         J = self._out((self.B,), np.float64)
         F = self._out((self.B,), np.float64)
@@ -386,7 +429,7 @@ class Problem:
 
 
 def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=None,
-                 io_device=False, set_u=True, step_map="exp"):
+                 io_device=False, set_u=True, step_map="exp", launch_per_pass=False):
     """Create a handle from a ``problems.FiniteProblem`` (or ``problems.GpeProblem``)."""
     if hasattr(prob, "V0"):
         B = prob.batch if batch is None else batch
@@ -403,7 +446,8 @@ def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=No
     p = Problem.create(H0, prob.Hc, prob.psi0, prob.target, prob.T, prob.K,
                        prob.N if N is None else N, precision=precision, kind=prob.kind, batch=B,
                        h0_batched=prob.H0.ndim == 3, alpha=al, device=device, stream=stream,
-                       io_device=io_device, step_map=step_map)
+                       io_device=io_device, step_map=step_map,
+                       launch_per_pass=launch_per_pass)
     if set_u:
         p.set_controls(prob.u0[:B])
     return p

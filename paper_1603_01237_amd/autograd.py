@@ -9,6 +9,9 @@ g = (1/tau) dJ/du (Theorem 2 assembles it slice-parallel).  The autograd gradien
 therefore dJ/du = tau g.
 
 The handle must be created with io_device=True (controls and gradients stay on the GPU).
+Its stream is ordered against torch's current stream in both directions around every
+library call (the controls are ready before the library reads them; J and the gradient are
+ready before torch reads them), so forward and backward may run under any torch stream.
 """
 from __future__ import annotations
 
@@ -29,8 +32,11 @@ class ISMObjective(torch.autograd.Function):
         if u.dtype != torch.float64 or not u.is_cuda:
             raise TypeError("controls must be a float64 CUDA tensor")
         uc = u.detach().contiguous()
+        cur, hs = torch.cuda.current_stream(), handle.torch_stream
+        hs.wait_stream(cur)               # uc is written on cur
         handle.set_controls(uc)
         J, _ = handle.fidelity()
+        cur.wait_stream(hs)               # J is written on the handle's stream
         ctx.handle = handle
         ctx.version = handle.version
         ctx.save_for_backward(uc)
@@ -40,9 +46,12 @@ class ISMObjective(torch.autograd.Function):
     def backward(ctx, gJ: torch.Tensor):
         (uc,) = ctx.saved_tensors
         h: Problem = ctx.handle
+        cur, hs = torch.cuda.current_stream(), h.torch_stream
+        hs.wait_stream(cur)
         if h.version != ctx.version:      # the handle was reused: restore this graph's controls
             h.set_controls(uc)
         g = h.gradient()                  # (1/tau) dJ/du, device tensor
+        cur.wait_stream(hs)
         tau = h.T / h.K
         return gJ.to(g.dtype)[:, None, None] * g * tau, None
 

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libism.so")
 
 SOURCES = ["ism_api.cpp", "ism_server.cpp", "k_sparse.hip", "k_gate.hip", "k_gpe.hip",
-           "ism_static.hip"]
+           "ism_static.hip", "k_small.hip", "ism_newton.cpp", "k_newton.hip"]
 
 ARCH = os.environ.get("ISM_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

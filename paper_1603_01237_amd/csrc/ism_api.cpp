@@ -55,7 +55,7 @@ namespace ism {
 const char* const kKernelNames[KID_COUNT] = {
     "sp_params", "sp_assemble", "sp_boundary", "sp_slice", "check_finite",
     "gate_build", "gate_gemm", "gate_grad", "gate_boundary",
-    "gpe_sweep", "gpe_slice", "gpe_boundary", "sp_sweep", "err"};
+    "gpe_sweep", "gpe_slice", "gpe_boundary", "sp_sweep", "err", "small_solve"};
 
 static hipEvent_t pool_get(ism_problem* p) {
     if (!p->event_pool.empty()) {
@@ -140,6 +140,7 @@ int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism
     p->device = o->device;
     p->io_device = o->io_device;
     p->async_alloc = o->alloc_async != 0;
+    p->launch_per_pass = o->launch_per_pass != 0;
     ISM_TRY_HIP(hipSetDevice(o->device));
     if (o->stream) {
         p->stream = (hipStream_t)o->stream;
@@ -272,6 +273,12 @@ static int sp_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bo
 }
 
 static int sp_slice_pass(ism_problem* p, int update, double rho, double* grad, bool use_active) {
+    if (!p->tp_valid) {        // boundaries from the one-launch solve: no Taylor parameters yet
+        SpArgs ap = sp_args(p, 1);
+        TimeScope ts(p, KID_SP_PARAMS);
+        ISM_TRY_HIP(sp_launch_params(ap, p->h0norm, p->gnorm, p->precision, p->stream, p->flags));
+        p->tp_valid = true;
+    }
     SpArgs a = sp_args(p, 0);
     a.update = update;
     a.rho = rho;
@@ -386,6 +393,11 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
     const size_t msz = (size_t)B * p->N * d * d * 2 *
                        (p->precision == ISM_FP64 ? sizeof(double) : sizeof(float));
     if ((st = dev_alloc(p, &p->M, msz))) return st;
+    if (p->precision == ISM_FP64 && !p->step_cn && d <= kSmallD && C <= kSmallC &&
+        p->N <= kSmallN) {
+        if ((st = small_setup(p, H0, h0_batched, Hc))) return st;
+        p->small = true;
+    }
     return ISM_OK;
 }
 
@@ -395,7 +407,12 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
 
 int boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active) {
     switch (p->path) {
-        case PATH_SPARSE: return sp_boundary_pass(p, Jhist_k, fid_stop, use_active);
+        case PATH_SPARSE:
+            // small FP64 problems: the boundaries of the one-launch solve, so that every entry
+            // point sees the same J, F and intermediate states as its iterations
+            if (small_eligible(p))
+                return small_run(p, 0, 0.0, fid_stop, Jhist_k, nullptr, true, use_active);
+            return sp_boundary_pass(p, Jhist_k, fid_stop, use_active);
         case PATH_GATE: return gate_boundary_pass(p, Jhist_k, fid_stop, use_active);
         case PATH_GPE: return gpe_boundary_pass(p, Jhist_k, fid_stop, use_active);
     }
@@ -456,12 +473,16 @@ int serve_begin(ism_problem* p, double fid_stop) {
 // n more iterations, enqueued with no host synchronisation: each is the slice pass with
 // the update u += rho g (skipped by frozen instances) followed by the boundary pass at the
 // new controls, so after the chunk J and F belong to the current u.  flags[1] counts the
-// instances still active after each of the n boundary passes.
-int serve_chunk(ism_problem* p, int n, double rho, double fid_stop) {
+// instances still active after each of the n boundary passes; count (device, nullable)
+// accumulates per instance the updates it took.
+int serve_chunk(ism_problem* p, int n, double rho, double fid_stop, int* count) {
     int st;
     ISM_TRY_HIP(hipMemsetAsync(p->flags, 0, 4 * sizeof(int), p->stream));
+    if (small_eligible(p)) return small_run(p, n, rho, fid_stop, nullptr, count, false, true);
     for (int k = 0; k < n; ++k) {
         if ((st = slice_pass(p, 1, rho, nullptr, true))) return st;
+        // the instances active in this slice pass took an update
+        if (count) ISM_TRY_HIP(launch_count_active(count, p->active, p->B, p->stream));
         if ((st = boundary_pass(p, nullptr, fid_stop, true))) return st;
     }
     return ISM_OK;
@@ -487,6 +508,7 @@ void ism_default_options(ism_options* o) {
     o->io_device = 0;
     o->alloc_async = 0;
     o->step_map = ISM_STEP_EXP;
+    o->launch_per_pass = 0;
 }
 
 const char* ism_status_string(int s) {
@@ -552,9 +574,7 @@ int ism_problem_create(ism_problem** out, int d, int n_ctrl, const double* H0, c
     if (!p) return ISM_E_NOMEM;
     st = common_setup(p, d, n_ctrl, T, K, N, &o);
     if (!st) {
-        if (dense && p->step_cn) {
-            st = ISM_E_UNSUPPORTED;
-        } else if (dense) {
+        if (dense) {
             p->path = PATH_GATE;
             st = gate_create(p, H0, o.h0_batched, Hc, psi0, target);
         } else {
@@ -657,9 +677,12 @@ int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, doubl
         p->Errhist_cap = (int)need;
     }
     int done = 0;
-    if ((st = iterate_loop(p, n_iter, n_inner, rho, fid_stop, err_stop, p->Jhist,
-                           want_err ? p->Errhist : nullptr, false, &done)))
+    if (n_inner == 1 && !want_err && small_eligible(p)) {
+        if ((st = small_iterate(p, n_iter, rho, fid_stop, p->Jhist, &done))) return st;
+    } else if ((st = iterate_loop(p, n_iter, n_inner, rho, fid_stop, err_stop, p->Jhist,
+                                  want_err ? p->Errhist : nullptr, false, &done))) {
         return st;
+    }
     if (J_hist && n_iter > 0) {
         if ((st = copy_out(p, J_hist, p->Jhist, (size_t)n_iter * p->B * sizeof(double)))) return st;
     }
@@ -673,6 +696,28 @@ int ism_iterate_inner(ism_problem* p, int n_iter, int n_inner, double rho, doubl
 }  // extern "C"
 
 namespace ism {
+
+// ism_iterate as one launch (small FP64 state problems): active flags, flags and update
+// counters cleared by fills, n_iter iterations, one host wait; done = the most updates any
+// instance took, which is the iteration at which the per-pass loop ends.  Allocates nothing
+// (ism_iterate_static uses it with its fixed history array).
+int small_iterate(ism_problem* p, int n_iter, double rho, double fid_stop, double* jbuf,
+                  int* done_out) {
+    int st;
+    *done_out = 0;
+    if (n_iter == 0) return ISM_OK;
+    ISM_TRY_HIP(launch_fill_i32(p->active, 1, p->B, p->stream));
+    ISM_TRY_HIP(launch_fill_i32(p->flags, 0, 4, p->stream));
+    ISM_TRY_HIP(launch_fill_i32(p->sm_count, 0, p->B, p->stream));
+    if ((st = small_run(p, n_iter, rho, fid_stop, jbuf, p->sm_count, true, true))) return st;
+    ISM_TRY_HIP(small_launch_done(p));
+    int fl[4];
+    if ((st = read_flags(p, fl))) return st;
+    if (fl[0] & 2) return ISM_E_UNSUPPORTED;
+    if (fl[0]) return ISM_E_NUMERIC;
+    *done_out = fl[2];
+    return ISM_OK;
+}
 
 // The iteration loop of Algorithm 1 (steps (a)-(e)) on history buffers the caller provides:
 // jbuf holds n_iter * B doubles, ebuf (null unless Err is wanted) as many.  With `fills` the
@@ -844,6 +889,9 @@ size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kin
     bytes += 3 * B * (N + 1) * dd * 16;              // Psi, Lam, phi
     bytes += B * N * dd * dd * 2 * rs;               // slice propagators
     bytes += (size_t)(n_ctrl + 1) * dd * 8 * 24 + B * 64;   // generators, params
+    if (precision == ISM_FP64)                       // one-launch solve of small problems
+        bytes += small_workspace_bytes(d, n_ctrl, K, N, batch) + B * 32 +
+                 (size_t)batch * (n_ctrl + 1) * kSmallD * kSmallD * 16;
     return bytes;
 }
 

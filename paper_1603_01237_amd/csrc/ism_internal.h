@@ -15,6 +15,27 @@ struct dcx { double re, im; };   // interleaved complex, same layout as the ABI'
 
 // largest Taylor degree of the tridiagonal kernels, whose Horner series are unrolled
 constexpr int kTriMaxTerms = 12;
+// limits of the one-launch solve of small FP64 state problems (k_small.hip)
+constexpr int kSmallD = 4, kSmallC = 4, kSmallN = 64;
+// most GMRES steps of the Newton slice solver (ism_newton.cpp)
+constexpr int kNewtonMaxM = 32;
+
+// device buffers of the Newton slice solver, kept by the handle for the GMRES size m
+struct NewtonBufs {
+    int m = 0;
+    double* V = nullptr;     // (m + 1) x BKC Arnoldi vectors
+    double* G = nullptr;     // BKC: slice gradients at u^(k)
+    double* Gp = nullptr;    // BKC
+    double* Gm = nullptr;    // BKC
+    double* W = nullptr;     // BKC
+    double* u0 = nullptr;    // BKC
+    double* H = nullptr;     // B N (m + 1) m Hessenberg matrices, column-major per slice
+    double* beta = nullptr;  // B N
+    double* wn = nullptr;    // B N: ||A v_i||^2 before the orthogonalisation
+    double* nn = nullptr;    // B N
+    double* y = nullptr;     // B N m
+    int* kdim = nullptr;     // B N: Krylov dimension at a breakdown, -1 otherwise
+};
 struct fcx { float re, im; };
 
 enum Path { PATH_SPARSE = 0, PATH_GATE = 1, PATH_GPE = 2 };
@@ -82,7 +103,8 @@ struct BndArgs {
 enum KernelId {
     KID_SP_PARAMS = 0, KID_SP_ASSEMBLE, KID_SP_BOUNDARY, KID_SP_SLICE, KID_CHECK,
     KID_GATE_BUILD, KID_GATE_GEMM, KID_GATE_GRAD, KID_GATE_BOUNDARY,
-    KID_GPE_SWEEP, KID_GPE_SLICE, KID_GPE_BOUNDARY, KID_SP_SWEEP, KID_ERR, KID_COUNT
+    KID_GPE_SWEEP, KID_GPE_SLICE, KID_GPE_BOUNDARY, KID_SP_SWEEP, KID_ERR, KID_SMALL_SOLVE,
+    KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -164,6 +186,20 @@ struct ism_problem {
     ism::dcx* Lam = nullptr;
     ism::dcx* phi = nullptr;
     void* M = nullptr;
+
+    // one-launch solve of small FP64 state problems (k_small.hip)
+    int launch_per_pass = 0;   // option: never use it
+    bool small = false;        // set up at create (d, C, N within its limits)
+    ism::dcx* sm_h = nullptr;  // (1 + C) padded generators per H0 instance, H0 shifted
+    long long sm_hstride = 0;
+    double* sm_shift = nullptr;
+    double* sm_xnorm = nullptr;
+    double* sm_cnorm = nullptr;
+    ism::dcx* sm_work = nullptr;
+    int* sm_count = nullptr;
+
+    // Newton slice solver (ism_newton.cpp)
+    ism::NewtonBufs nw;
 
     // per-kernel timing
     bool timing = false;

@@ -1,4 +1,5 @@
-// Allocation-free iteration entry point (ism_iterate_static) and the fill kernel it uses.
+// Allocation-free iteration entry point (ism_iterate_static), and two small utility kernels:
+// a fill (flags and counters) and a per-instance update counter (serving).
 //
 // ism_iterate keeps the per-iteration J history that the boundary kernels write in a device
 // buffer it grows per handle.  ism_iterate_static runs the same launch sequence with that
@@ -45,11 +46,22 @@ __global__ void k_fill_i32(int* x, int v, int n) {
     if (i < n) x[i] = v;
 }
 
+__global__ void k_count_active(int* count, const int* active, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) count[i] += active[i] != 0;
+}
+
 }  // namespace
 
 hipError_t launch_fill_i32(int* x, int v, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, x, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_active(int* count, const int* active, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_active, dim3((n + 255) / 256), dim3(256), 0, st, count, active, n);
     return hipGetLastError();
 }
 
@@ -66,8 +78,11 @@ extern "C" int ism_iterate_static(ism_problem* p, int n_iter, double rho, double
     int st = scratch_on(p->device, &jbuf);
     if (st) return st;
     int done = 0;
-    if ((st = iterate_loop(p, n_iter, 1, rho, fid_stop, 0.0, jbuf, nullptr, true, &done)))
+    if (small_eligible(p)) {
+        if ((st = small_iterate(p, n_iter, rho, fid_stop, jbuf, &done))) return st;
+    } else if ((st = iterate_loop(p, n_iter, 1, rho, fid_stop, 0.0, jbuf, nullptr, true, &done))) {
         return st;
+    }
     // the rows the loop wrote: J^(k) for k < done, and J^(done) when it stopped early
     const int rows = std::min(n_iter, done + 1);
     if (J_hist && rows > 0) {

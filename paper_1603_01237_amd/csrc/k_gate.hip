@@ -209,13 +209,15 @@ struct GateGen {
     const int* col;          // d*W column of each stored entry (padding: own row)
     const dcx* h0v;          // d*W  values of H0 - s I
     const dcx* hcu;          // C*d*W values of H_c on the union pattern
-    const int* ccol;         // C*d*WCc per-control columns
-    const dcx* cval;         // C*d*WCc per-control values
-    int WCc;
+    const int* wq;           // d*W*CW: the controls with an entry at position w of row r's
+                             // union pattern (padding: control 0 with value 0)
+    const dcx* wv;           // d*W*CW: those entries of H_c
+    int CW;
     const double* u;         // K*C
     double tau, shift;
     double h0norm;           // || H0 - s ||_inf
     const double* cnorm;     // C  || H_c ||_inf
+    int cn;                  // 1: Crank-Nicolson (Cayley) step map, no spectral shift (s = 0)
 };
 
 __device__ __forceinline__ int taylor_terms(double theta, double tol, int& S) {
@@ -233,6 +235,20 @@ __device__ __forceinline__ int taylor_terms(double theta, double tol, int& S) {
         ++m;
     }
     return m;
+}
+
+// Terms of the Neumann series sum_k (-L)^k of (I + L)^{-1}, ||L|| <= theta, until the
+// remainder theta^(n+1) / (1 - theta) is below tol; -1 beyond the useful range (theta at
+// least `lim`: 0.25 in FP64, 0.45 in FP32), which is reported, never truncated.
+__device__ __forceinline__ int neumann_terms(double theta, double tol, double lim) {
+    if (!(theta < lim)) return -1;
+    int n = 1;
+    double rem = theta * theta / (1.0 - theta);
+    while (n < 64 && rem > tol) {
+        ++n;
+        rem *= theta;
+    }
+    return rem > tol ? -1 : n;
 }
 
 // Krylov order of the gradient series at step j (at most cap): the dropped terms
@@ -285,12 +301,24 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
     // FP64 path: truncation below FP64 rounding.  FP32 path (U_j stored in FP32): the
     // truncation summed over the K steps below 1e-5, never above 1e-8 per step
     const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
-    int m = taylor_terms(theta, tol, S);
-    if (m < 0) {
-        if (t == 0 && blockIdx.y == 0) atomicOr(flags, 1);
-        m = 1;
+    int m;
+    if (gg.cn) {
+        // Crank-Nicolson: D_j = U_j - I = -2 (I + L_j)^{-1} L_j = 2 sum_{k >= 1} (-L_j)^k,
+        // L_j = (i tau/2) H_j, as a Neumann series (row r of D_j is that series of L_j^T on e_r)
+        S = 1;
+        m = neumann_terms(0.5 * theta, tol, sizeof(R) == 8 ? 0.25 : 0.45);
+        if (m < 0) {
+            if (t == 0 && blockIdx.y == 0) atomicOr(flags, theta == theta ? 2 : 1);
+            m = 1;
+        }
+    } else {
+        m = taylor_terms(theta, tol, S);
+        if (m < 0) {
+            if (t == 0 && blockIdx.y == 0) atomicOr(flags, 1);
+            m = 1;
+        }
     }
-    const double ts = gg.tau / S;
+    const double ts = gg.cn ? 0.5 * gg.tau : gg.tau / S;
 #pragma unroll
     for (int w = 0; w < WT; ++w) {
         dcx h = {0.0, 0.0};
@@ -328,7 +356,9 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
 #pragma unroll
                 for (int q = 0; q < RB; ++q) vs[q * VS + t] = tr[q];
                 __syncthreads();
-                const double rk = 1.0 / (k + 1);
+                // Taylor: -i (h x) / (k+1), all terms summed; Neumann: -i (h x), summed twice
+                const double rk = gg.cn ? 1.0 : 1.0 / (k + 1);
+                const double wk = gg.cn ? 2.0 : 1.0;
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
                     double ar = 0.0, ai = 0.0;
@@ -338,10 +368,10 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
                         ar = fma(hv[w].re, x.re, fma(-hv[w].im, x.im, ar));
                         ai = fma(hv[w].re, x.im, fma(hv[w].im, x.re, ai));
                     }
-                    tr[q].re = ai * rk;      // -i (h x) / (k+1)
+                    tr[q].re = ai * rk;
                     tr[q].im = -ar * rk;
-                    acc[q].re += tr[q].re;
-                    acc[q].im += tr[q].im;
+                    acc[q].re = fma(wk, tr[q].re, acc[q].re);
+                    acc[q].im = fma(wk, tr[q].im, acc[q].im);
                 }
                 __syncthreads();
             }
@@ -374,7 +404,7 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
             }
         }
     }
-    if (t == 0 && blockIdx.y == 0) {      // the gradient's Krylov order at this step
+    if (!gg.cn && t == 0 && blockIdx.y == 0) {   // the gradient's Krylov order at this step
         double rem;
         const int mj = grad_order<R>(gg, j, MMAX_G + 1, rem);
         // most steps need the same order: update only when it is above the value seen so far
@@ -852,6 +882,19 @@ __device__ constexpr WabTable kWab = make_wab();
 // time) unless d <= 32, where lpc is the least power of two >= d and a workgroup of dp = 64
 // threads takes 64 / lpc columns at once (rows d..dp-1 of the padded layout are never
 // worked on).  Slot t of every LDS vector belongs to thread t.
+//
+// With Hhat_c = sum_{a,b} w_ab (i tau H')^a H_c (-i tau H')^b / tau^0 (the series of the step
+// average, H' = H_j - s), <y|Hhat_c|x> = sum_b <t_b| H_c r_b> with p_a = (tau H')^a y,
+// r_b = (tau H')^b x and t_b = sum_a conj(w_ab) p_a.  Two Krylov phases per column, each
+// through one double-buffered LDS vector (one barrier per Krylov step):
+//   (1) p_a, a = 0..m, folded into the t_b (registers) as they are produced;
+//   (2) r_b, b = 0..m: the gathers that form r_{b+1} read r_b at every column w of this
+//       row's union pattern, which is where the controls' entries lie; they are folded into
+//       S_w = sum_b conj(t_b) r_b(col_w) at once.
+// Then Im <t|H_c r> over this row is Im sum h_{c,w} S_w over the control's entries of the
+// row (wq, wv list them per position of the union pattern).  Neither phase keeps a Krylov
+// sequence in LDS.
+//
 // A step whose series, cut at MK terms, leaves a remainder bound above 1e-13 (FP64) or 1e-7
 // (FP32) sets bit 1 of flags[0] (reported as unsupported, never truncated silently):
 // 2 tau ||H_j - s||_inf above 1.46 in FP64 or 2.0 in FP32.
@@ -859,18 +902,18 @@ __device__ constexpr WabTable kWab = make_wab();
 // most mks (kmax, from the step build at the same controls; then the order of every step is
 // the same as with the larger bound, and so is the result), the other one otherwise.  The
 // smaller bound holds fewer registers and more wavefronts per SIMD.
-template <typename R, int MK, int WT>
-__global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
+template <typename R, int MK, int WT, int VS, int NC>
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
                                                    double* gpart, int ncb, int* flags,
                                                    const int* kmax, int mks) {
     if ((*kmax <= mks) != (MK == mks)) return;      // the other bound's launch does this work
-    // LDS: per-row gradient accumulators of every control; Krylov vectors (tau H')^b x,
-    // b = 0..MK, as re/im planes; a double buffer for the Krylov vectors of y; the
-    // per-wavefront partial sums of the final reduction.
+    // LDS: per-row gradient accumulators of every control (FP64, thread t's slots only) and,
+    // for each of the NC columns a thread works on at once, a Krylov double buffer (2 x re/im
+    // planes), at a compile-time plane stride VS >= dp so that every gather of a row needs
+    // one address and immediate offsets
     extern __shared__ unsigned char smem_raw[];
-    double* gacc = reinterpret_cast<double*>(smem_raw);          // C dp
-    R* kv = reinterpret_cast<R*>(gacc + (size_t)gg.C * gg.dp);  // 2 (MK+1) dp
-    R* yb = kv + 2 * (MK + 1) * gg.dp;                          // 2 x 2 dp
+    double* gacc = reinterpret_cast<double*>(smem_raw);          // C VS
+    R* vb = reinterpret_cast<R*>(gacc + (size_t)gg.C * VS);     // 4 NC VS
     __shared__ double red[4][CMAX_G];
     const int j = blockIdx.x, cb = blockIdx.y, t = threadIdx.x;
     const int d = gg.d, dp = gg.dp;
@@ -909,98 +952,144 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
         hvi[w] = (R)(gg.tau * hi);
         hcol[w] = cc;
     }
-    for (int q = 0; q < gg.C; ++q) gacc[q * dp + t] = 0.0;     // own slots only
-    for (int kk = 0; kk < CBW; kk += ngrp) {
+    for (int q = 0; q < gg.C; ++q) gacc[q * VS + t] = 0.0;     // own slots only
+    // Krylov buffer `buf` (0/1) of column slot `c`, plane 0 (re) or 1 (im)
+    auto vbp = [&](int c, int buf, int plane) { return vb + ((c * 2 + buf) * 2 + plane) * VS; };
+    for (int kk = 0; kk < CBW; kk += ngrp * NC) {
         if (cb * CBW + kk >= d) break;        // uniform over the workgroup
-        // column k of X_j (x) and Y_j (y) for this thread's group
+        // columns k_c of X_j (x) and Y_j (y) for this thread's group, c < NC
         // stored as [X_j | Y_j]^+: column k of X_j is row k, conjugated; of Y_j row dp + k
-        const int k = cb * CBW + kk + grp;
-        const bool live = r < d && k < d && kk + grp < CBW;
-        const long long ox = (long long)j * xy_plane * 2 + (long long)k * dp + r;
-        const long long oy = ox + (long long)dp * dp;
-        R xr = live ? XY[ox] : R(0), xi = live ? -XY[ox + xy_plane] : R(0);
-        R yr = live ? XY[oy] : R(0), yi = live ? -XY[oy + xy_plane] : R(0);
-        __syncthreads();                      // the previous column's readers of kv are done
-        kv[t] = xr;
-        kv[dp + t] = xi;
-        yb[t] = yr;
-        yb[dp + t] = yi;
-        // t_b = sum_a conj(w_ab) p_a, p_a = (tau H')^a y, with
-        // conj(w_ab) = (-i)^{a+b} (-1)^b |w_ab|, accumulated as the p_a are produced
-        R ttr[MK + 1], tti[MK + 1];
+        R xr[NC], xi[NC], yr[NC], yi[NC];
+        bool live[NC];
 #pragma unroll
-        for (int b = 0; b <= MK; ++b) ttr[b] = tti[b] = 0;
+        for (int c = 0; c < NC; ++c) {
+            const int kc = kk + c * ngrp + grp;
+            const int k = cb * CBW + kc;
+            live[c] = r < d && k < d && kc < CBW;
+            const long long ox = (long long)j * xy_plane * 2 + (long long)k * dp + r;
+            const long long oy = ox + (long long)dp * dp;
+            xr[c] = live[c] ? XY[ox] : R(0);
+            xi[c] = live[c] ? -XY[ox + xy_plane] : R(0);
+            yr[c] = live[c] ? XY[oy] : R(0);
+            yi[c] = live[c] ? -XY[oy + xy_plane] : R(0);
+        }
+        // phase 1: p_a = (tau H')^a y; t_b += conj(w_ab) p_a, conj(w_ab) = (-i)^{a+b} (-1)^b |w_ab|
+        R ttr[NC][MK + 1], tti[NC][MK + 1];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int b = 0; b <= MK; ++b) ttr[c][b] = tti[c][b] = 0;
+        __syncthreads();                      // the previous columns' readers of vb are done
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            vbp(c, 0, 0)[t] = yr[c];
+            vbp(c, 0, 1)[t] = yi[c];
+        }
 #pragma unroll
         for (int a = 0; a <= MK; ++a) {
-            if (a > 0) {
-                // Krylov step a of x and y (every thread reaches the barrier every time)
-                __syncthreads();
-                const R* xs = kv + 2 * (a - 1) * dp + base;
-                const R* ys = yb + 2 * ((a - 1) & 1) * dp + base;
-                R nxr = 0, nxi = 0, nyr = 0, nyi = 0;
-                if (a <= m) {
+            if (a <= m) {                     // m is uniform over the workgroup
+                if (a > 0) {
+                    __syncthreads();          // p_{a-1} is in buffer (a-1) & 1
 #pragma unroll
-                    for (int w = 0; w < WT; ++w) {
-                        const int cc = hcol[w];
-                        const R ur = xs[cc], ui = xs[dp + cc], vr = ys[cc], vi = ys[dp + cc];
-                        nxr = fma(hvr[w], ur, fma(-hvi[w], ui, nxr));
-                        nxi = fma(hvr[w], ui, fma(hvi[w], ur, nxi));
-                        nyr = fma(hvr[w], vr, fma(-hvi[w], vi, nyr));
-                        nyi = fma(hvr[w], vi, fma(hvi[w], vr, nyi));
+                    for (int c = 0; c < NC; ++c) {
+                        const R* ysr = vbp(c, (a - 1) & 1, 0) + base;
+                        const R* ysi = vbp(c, (a - 1) & 1, 1) + base;
+                        R nyr = 0, nyi = 0;
+#pragma unroll
+                        for (int w = 0; w < WT; ++w) {
+                            const int cc = hcol[w];
+                            const R vr = ysr[cc], vi = ysi[cc];
+                            nyr = fma(hvr[w], vr, fma(-hvi[w], vi, nyr));
+                            nyi = fma(hvr[w], vi, fma(hvi[w], vr, nyi));
+                        }
+                        if (a < m) {          // p_m is read by nobody
+                            vbp(c, a & 1, 0)[t] = nyr;
+                            vbp(c, a & 1, 1)[t] = nyi;
+                        }
+                        yr[c] = nyr;
+                        yi[c] = nyi;
                     }
-                    kv[2 * a * dp + t] = nxr;
-                    kv[(2 * a + 1) * dp + t] = nxi;
-                    yb[2 * (a & 1) * dp + t] = nyr;
-                    yb[(2 * (a & 1) + 1) * dp + t] = nyi;
                 }
-                yr = nyr;
-                yi = nyi;
-            }
-            if (a <= m) {
 #pragma unroll
                 for (int b = 0; b + a <= MK; ++b) {
                     if (a + b <= m) {
                         R wr = (R)kWab.v[a][b];
                         if (b & 1) wr = -wr;
                         const int ph = (a + b) & 3;
-                        const R qr = ph == 0 ? yr : ph == 1 ? yi : ph == 2 ? -yr : -yi;
-                        const R qi = ph == 0 ? yi : ph == 1 ? -yr : ph == 2 ? -yi : yr;
-                        ttr[b] = fma(wr, qr, ttr[b]);
-                        tti[b] = fma(wr, qi, tti[b]);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            const R qr = ph == 0 ? yr[c] : ph == 1 ? yi[c] : ph == 2 ? -yr[c] : -yi[c];
+                            const R qi = ph == 0 ? yi[c] : ph == 1 ? -yr[c] : ph == 2 ? -yi[c] : yr[c];
+                            ttr[c][b] = fma(wr, qr, ttr[c][b]);
+                            tti[c][b] = fma(wr, qi, tti[c][b]);
+                        }
                     }
                 }
             }
         }
-        __syncthreads();                      // all Krylov vectors of x are in kv
-        // per control: Im of sum_b conj(t_b) (H_c r_b)_row
-        if (live) {
-            for (int q = 0; q < gg.C; ++q) {
-                double sacc = 0.0;
-                for (int wc = 0; wc < gg.WCc; ++wc) {
-                    const size_t ci = ((size_t)q * d + r) * gg.WCc + wc;
-                    const int cc = gg.ccol[ci];
-                    const dcx hv = gg.cval[ci];
-                    // s = sum_b conj(t_b) r_b(cc) in the path precision, then
-                    // Im(s h) = Im(conj(t_b) h r_b) summed, accumulated in FP64
-                    R sr = 0, si = 0;
+        // phase 2: r_b = (tau H')^b x; S_w += conj(t_b) r_b(col_w)
+        R swr[NC][WT], swi[NC][WT];
 #pragma unroll
-                    for (int b = 0; b <= MK; ++b) {
-                        if (b <= m) {
-                            const R rr = kv[(2 * b) * dp + base + cc], ri = kv[(2 * b + 1) * dp + base + cc];
-                            sr = fma(ttr[b], rr, fma(tti[b], ri, sr));
-                            si = fma(ttr[b], ri, fma(-tti[b], rr, si));
-                        }
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int w = 0; w < WT; ++w) swr[c][w] = swi[c][w] = 0;
+        __syncthreads();                      // phase 1's readers of vb are done
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            vbp(c, 0, 0)[t] = xr[c];
+            vbp(c, 0, 1)[t] = xi[c];
+        }
+#pragma unroll
+        for (int b = 0; b <= MK; ++b) {
+            if (b <= m) {
+                __syncthreads();              // r_b is in buffer b & 1
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const R* xsr = vbp(c, b & 1, 0) + base;
+                    const R* xsi = vbp(c, b & 1, 1) + base;
+                    const R cr = ttr[c][b], ci = tti[c][b];
+                    R nxr = 0, nxi = 0;
+#pragma unroll
+                    for (int w = 0; w < WT; ++w) {
+                        const int cc = hcol[w];
+                        const R ur = xsr[cc], ui = xsi[cc];
+                        swr[c][w] = fma(cr, ur, fma(ci, ui, swr[c][w]));
+                        swi[c][w] = fma(cr, ui, fma(-ci, ur, swi[c][w]));
+                        nxr = fma(hvr[w], ur, fma(-hvi[w], ui, nxr));
+                        nxi = fma(hvr[w], ui, fma(hvi[w], ur, nxi));
                     }
-                    sacc += hv.re * (double)si + hv.im * (double)sr;
+                    if (b < m) {
+                        vbp(c, (b + 1) & 1, 0)[t] = nxr;
+                        vbp(c, (b + 1) & 1, 1)[t] = nxi;
+                    }
                 }
-                gacc[q * dp + t] += sacc;
+            }
+        }
+        // per control: Im(h S_w) summed over the control's entries of this row, in FP64
+#pragma unroll
+        for (int w = 0; w < WT; ++w) {
+            if (w < gg.W && r < d) {
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if (live[c]) {
+                        sr += (double)swr[c][w];
+                        si += (double)swi[c][w];
+                    }
+                }
+                const size_t e0 = ((size_t)r * gg.W + w) * gg.CW;
+                for (int e = 0; e < gg.CW; ++e) {
+                    const int q = gg.wq[e0 + e];
+                    const dcx hv = gg.wv[e0 + e];
+                    gacc[q * VS + t] += hv.re * si + hv.im * sr;
+                }
             }
         }
     }
-    // reduction over rows: wavefront tree, then the four partials in order
+    // reduction over rows: wavefront tree, then the partials of the wavefronts in order
     const int wv = t >> 6, lane = t & 63;
     for (int q = 0; q < gg.C; ++q) {
-        double v = gacc[q * dp + t];
+        double v = gacc[q * VS + t];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) red[wv][q] = v;
     }
@@ -1011,6 +1100,142 @@ __global__ __launch_bounds__(256) void k_gate_grad(GateGen gg, const R* XY, long
         gpart[((size_t)j * ncb + cb) * gg.C + t] = s;
     }
 }
+// Crank-Nicolson gradient on the dense path (Sec. 3 with the reading of the discrete
+// gradient): per step j and column k of X_j (x) and Y_j (y), Im <A y| H_c |A x> with
+// A = (I + L_j)^{-1}, L_j = (i tau/2) H_j; with psi_j + psi_{j+1} = 2 A psi_j and
+// chi_j = (I - L_j)^{-1} lambda_{j+1} = A lambda_j this is the exact gradient
+// 1/2 Im <chi_j|H_c|psi_j + psi_{j+1}> (density matrices: 2 Im Tr((A Y)^+ H_c (A X)), the
+// factor applied by k_gate_grad_finish).  A v = sum_a (-L)^a v is a Neumann series whose
+// terms run through one double-buffered LDS vector (one barrier per term); the sum of y's
+// stays in registers, the sum of x's goes to LDS once for the gathers of H_c.  Same layout,
+// column blocking and partial sums as k_gate_grad.
+template <typename R, int WT, int VS>
+__global__ __launch_bounds__(256) void k_gate_grad_cn(GateGen gg, const R* XY, long long xy_plane,
+                                                      double* gpart, int ncb, int* flags) {
+    extern __shared__ unsigned char smem_raw[];
+    double* gacc = reinterpret_cast<double*>(smem_raw);          // C VS
+    R* vb = reinterpret_cast<R*>(gacc + (size_t)gg.C * VS);     // 6 VS: 2 buffers + the sum of x
+    __shared__ double red[4][CMAX_G];
+    const int j = blockIdx.x, cb = blockIdx.y, t = threadIdx.x;
+    const int d = gg.d, dp = gg.dp;
+    int lpc = dp;
+    if (d <= 32) {
+        lpc = 1;
+        while (lpc < d) lpc <<= 1;
+    }
+    const int r = t & (lpc - 1), base = t - r, grp = t / lpc, ngrp = dp / lpc;
+    const double* uj = gg.u + (size_t)j * gg.C;
+    int nt;
+    {
+        double bound = gg.h0norm;
+        for (int q = 0; q < gg.C; ++q) bound += fabs(uj[q]) * gg.cnorm[q];
+        const double tol = sizeof(R) == 8 ? 1e-17 : fmin(1e-8, 1e-5 / (double)gg.K);
+        nt = neumann_terms(0.5 * gg.tau * bound, tol, sizeof(R) == 8 ? 0.25 : 0.45);
+        if (nt < 0) {
+            if (t == 0 && cb == 0) atomicOr(flags, 2);
+            nt = 1;
+        }
+    }
+    // row r of (tau/2) H_j on the union pattern
+    R hvr[WT], hvi[WT];
+    int hcol[WT];
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        double hr = 0.0, hi = 0.0;
+        int cc = r;
+        if (r < d && w < gg.W) {
+            const size_t idx = (size_t)r * gg.W + w;
+            hr = gg.h0v[idx].re;
+            hi = gg.h0v[idx].im;
+            for (int q = 0; q < gg.C; ++q) {
+                const dcx x = gg.hcu[(size_t)q * d * gg.W + idx];
+                hr += uj[q] * x.re;
+                hi += uj[q] * x.im;
+            }
+            cc = gg.col[idx];
+        }
+        hvr[w] = (R)(0.5 * gg.tau * hr);
+        hvi[w] = (R)(0.5 * gg.tau * hi);
+        hcol[w] = cc;
+    }
+    for (int q = 0; q < gg.C; ++q) gacc[q * VS + t] = 0.0;     // own slots only
+    // v <- A v = sum_a (-L)^a v through the double buffer; returns the sum
+    auto neumann = [&](R vr, R vi, R& sr, R& si) {
+        sr = vr;
+        si = vi;
+        vb[t] = vr;
+        vb[VS + t] = vi;
+        for (int a = 1; a <= nt; ++a) {          // nt is uniform over the workgroup
+            __syncthreads();                     // term a-1 is in buffer (a-1) & 1
+            const R* pr = vb + 2 * ((a - 1) & 1) * VS + base;
+            R hr = 0, hi = 0;
+#pragma unroll
+            for (int w = 0; w < WT; ++w) {
+                const int cc = hcol[w];
+                const R xr = pr[cc], xi = pr[VS + cc];
+                hr = fma(hvr[w], xr, fma(-hvi[w], xi, hr));
+                hi = fma(hvr[w], xi, fma(hvi[w], xr, hi));
+            }
+            // -L v = -i (tau/2) H v
+            const R nr = hi, ni = -hr;
+            sr += nr;
+            si += ni;
+            if (a < nt) {
+                vb[2 * (a & 1) * VS + t] = nr;
+                vb[(2 * (a & 1) + 1) * VS + t] = ni;
+            }
+        }
+    };
+    for (int kk = 0; kk < CBW; kk += ngrp) {
+        if (cb * CBW + kk >= d) break;        // uniform over the workgroup
+        const int k = cb * CBW + kk + grp;
+        const bool live = r < d && k < d && kk + grp < CBW;
+        const long long ox = (long long)j * xy_plane * 2 + (long long)k * dp + r;
+        const long long oy = ox + (long long)dp * dp;
+        const R xr = live ? XY[ox] : R(0), xi = live ? -XY[ox + xy_plane] : R(0);
+        const R yr = live ? XY[oy] : R(0), yi = live ? -XY[oy + xy_plane] : R(0);
+        R ayr, ayi, axr, axi;
+        __syncthreads();                      // the previous column's readers of vb are done
+        neumann(yr, yi, ayr, ayi);
+        __syncthreads();                      // readers of the y terms are done
+        neumann(xr, xi, axr, axi);
+        vb[4 * VS + t] = axr;                 // A x, for the gathers of H_c
+        vb[5 * VS + t] = axi;
+        __syncthreads();
+        if (live) {
+            const R* ax = vb + 4 * VS + base;
+#pragma unroll
+            for (int w = 0; w < WT; ++w) {
+                if (w < gg.W) {
+                    const int cc = hcol[w];
+                    const R ur = ax[cc], ui = ax[VS + cc];
+                    // S_w = conj(A y)_r (A x)_{col_w}
+                    const double sr = (double)ayr * ur + (double)ayi * ui;
+                    const double si = (double)ayr * ui - (double)ayi * ur;
+                    const size_t e0 = ((size_t)r * gg.W + w) * gg.CW;
+                    for (int e = 0; e < gg.CW; ++e) {
+                        const int q = gg.wq[e0 + e];
+                        const dcx hv = gg.wv[e0 + e];
+                        gacc[q * VS + t] += hv.re * si + hv.im * sr;
+                    }
+                }
+            }
+        }
+    }
+    const int wv = t >> 6, lane = t & 63;
+    for (int q = 0; q < gg.C; ++q) {
+        double v = gacc[q * VS + t];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (t < gg.C) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][t];
+        gpart[((size_t)j * ncb + cb) * gg.C + t] = s;
+    }
+}
+
 // g_{j,c} = beta_n (1/d) sum_cb gpart - alpha_j u_{j,c}; update or write the gradient.
 // gscale: 1/d for evolution operators (<A|B> = Tr(A^+ B)/d); 2 for density matrices, where
 // Im Tr(Hhat [rho_j, lambda_j]) = 2 Im Tr(Y_j^+ Hhat X_j) with X_j = P_{j-1} phi_n and

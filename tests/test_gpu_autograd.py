@@ -106,3 +106,69 @@ def test_module_with_optimizer_improves_objective():
     J1 = m().item()
     assert J1 > J0 + 0.05
     h.close()
+
+
+def test_forward_backward_under_a_side_stream():
+    """Forward and backward issued under a non-default torch stream: the handle's stream is
+    ordered against it both ways, so J and the gradient equal those computed on the default
+    stream, bitwise; gradcheck passes under the side stream as well.  The controls are
+    produced by a torch kernel on the side stream right before the call, so an unordered
+    read would see stale values."""
+    import torch
+    from paper_1603_01237_amd.autograd import ISMObjective
+    _say("case side stream")
+    p = problems.rotor(batch=2, K=60, N=6, T=0.5)
+    h = _handle(p)
+    base = torch.tensor(p.u0, dtype=torch.float64, device="cuda")
+    u_ref = base.clone().requires_grad_(True)
+    J_ref = ISMObjective.apply(u_ref, h)
+    J_ref.sum().backward()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            u = base.clone().requires_grad_(True)     # written on the side stream
+            J = ISMObjective.apply(u, h)
+            J.sum().backward()
+            assert torch.equal(J, J_ref) and torch.equal(u.grad, u_ref.grad)
+        assert torch.autograd.gradcheck(lambda x: ISMObjective.apply(x, h),
+                                        (base.clone().requires_grad_(True),), eps=1e-6,
+                                        atol=1e-8, rtol=1e-6)
+    torch.cuda.synchronize()
+    h.close()
+
+
+def test_autograd_gate_synthesis_full_size():
+    """The gate-synthesis configuration with autograd (8-spin chain, d = 256, 16 controls,
+    K = 2000, N = 64): backward through ISMObjective checked by a central finite difference
+    of the forward J along a random direction (FP64, relative 1e-6; the difference step
+    1e-4 leaves a truncation near 1e-9 of the directional derivative), and the FP32 mixed
+    backward against the FP64 one (relative 1e-3)."""
+    import torch
+    from paper_1603_01237_amd.autograd import ISMObjective
+    _say("case autograd gate d256")
+    p = problems.spin_chain_gate()
+    grads = {}
+    for prec in ("fp64", "fp32"):
+        h = _handle(p, prec)
+        u = torch.tensor(p.u0, dtype=torch.float64, device="cuda", requires_grad=True)
+        J = ISMObjective.apply(u, h)
+        J.sum().backward()
+        grads[prec] = u.grad.detach().clone()
+        if prec == "fp64":
+            v = torch.tensor(np.random.default_rng(8).standard_normal(p.u0.shape),
+                             dtype=torch.float64, device="cuda")
+            v = v / torch.linalg.vector_norm(v)
+            eps = 1e-4
+            with torch.no_grad():
+                Jp = ISMObjective.apply(u.detach() + eps * v, h)
+                Jm = ISMObjective.apply(u.detach() - eps * v, h)
+            fd = ((Jp - Jm) / (2 * eps)).sum().item()
+            an = (grads[prec] * v).sum().item()
+            _say("directional", an, fd, abs(an - fd) / abs(fd))
+            assert abs(an - fd) <= 1e-6 * abs(fd)
+        h.close()
+    rel = (torch.linalg.vector_norm(grads["fp32"] - grads["fp64"]) /
+           torch.linalg.vector_norm(grads["fp64"])).item()
+    _say("fp32 vs fp64 backward", rel)
+    assert rel <= 1e-3

@@ -115,7 +115,7 @@ def test_dense_path_reports_steps_beyond_its_gradient_series():
         assert e.value.code == _lib.ISM_E_UNSUPPORTED
 
 
-def test_density_rejects_non_hermitian_and_cn():
+def test_density_rejects_non_hermitian():
     from paper_1603_01237_amd import _lib
     _say("case density args")
     p = problems.spin5_density(K=8, N=2)
@@ -126,9 +126,6 @@ def test_density_rejects_non_hermitian_and_cn():
     with pytest.raises(_lib.IsmError) as e:
         _lib.from_problem(q)
     assert e.value.code == _lib.ISM_E_ARG
-    with pytest.raises(_lib.IsmError) as e:
-        _lib.from_problem(p, step_map="cn")
-    assert e.value.code == _lib.ISM_E_UNSUPPORTED
 
 
 def test_density_five_spin_full_size():

@@ -1,8 +1,8 @@
 """Serving loop (libism server) on the GPU: every solve served in a mix of concurrent
-requests returns exactly what it returns when served alone and what ism_iterate returns
-on its own handle (same launches in the same order: bitwise equal controls), the
-iterates follow the oracle's plain gradient method, and admission respects the memory
-budget."""
+requests, alone or merged with others into one batched handle, returns exactly what it
+returns when served alone and what ism_iterate returns on its own handle (bitwise equal
+controls), the iterates follow the oracle's plain gradient method, and admission respects
+the memory budget."""
 import sys
 
 import numpy as np
@@ -155,3 +155,44 @@ def test_trace_replay_sample():
     _say(summ)
     assert summ["completed"] == len(items) and summ["failed"] == 0
     assert all(r["latency_s"] >= 0 and r["queue_s"] >= 0 for r in recs)
+
+
+def test_merged_requests_equal_their_lone_runs():
+    """Requests that differ only in the diagonal of H0 (rotors with their own rotational
+    constant and initial controls; two-spin transfers with their own initial controls, frozen
+    at different iterations by the fidelity rule) are admitted into one batched handle each;
+    every merged request returns bitwise what it returns alone and what ism_iterate returns
+    on its own handle.  Requests of another shape or stopping rule are not merged."""
+    from paper_1603_01237_amd import _lib
+    rot = [(problems.rotor(seed=40 + i, batch=1, jmax=20, T=1.0, K=300, N=12), 1.0, 6, 2.0,
+            "fp32") for i in range(5)]
+    spins = []
+    for i, scale in enumerate((0.5, 1.0, 2.0, 3.0)):       # different starts: they freeze apart
+        q = problems.spin2(seed=50 + i, K=100, N=4, T=2.0)
+        q.u0 = q.u0 * scale
+        spins.append((q, 0.5, 200, 0.9, "fp64"))
+    other = [(problems.rotor(seed=60, batch=1, jmax=20, T=1.0, K=301, N=12), 1.0, 6, 2.0, "fp32"),
+             (problems.rotor(seed=61, batch=1, jmax=20, T=1.0, K=300, N=12), 1.0, 5, 2.0, "fp32")]
+    items = rot + spins + other
+    _say("case serve merge", len(items))
+    res, st = _serve(items, ipr=4)
+    assert st["completed"] == len(items) and st["failed"] == 0
+    assert st["merged"] == (len(rot) - 1) + (len(spins) - 1), st
+    assert st["groups"] == 2 + len(other), st
+    iters_spins = set()
+    for k, it in enumerate(items):
+        alone, _ = _serve([it], ipr=4)
+        rm, um = res[k]
+        ra, ua = alone[0]
+        assert rm["state"] == _lib.REQ_DONE and ra["state"] == _lib.REQ_DONE
+        assert rm["iters"] == ra["iters"], (k, rm, ra)
+        assert np.array_equal(um, ua), k
+        assert rm["F"] == ra["F"] and rm["J"] == ra["J"], k
+        p, rho, mi, fs, pr = it
+        with _lib.from_problem(p, precision=pr) as h:
+            _, done = h.iterate(mi, rho, fid_stop=fs)
+            assert done == rm["iters"]
+            assert np.array_equal(h.get_controls()[0], um), k
+        if len(rot) <= k < len(rot) + len(spins):
+            iters_spins.add(rm["iters"])
+    assert len(iters_spins) > 1           # the merged spins froze at different iterations
