@@ -115,6 +115,17 @@ typedef struct ism_options {
                                per instance holding every phase of Algorithm 1; 1: always the
                                sequence of per-pass launches.  Both give the iterates of
                                Algorithm 1 to FP64 rounding (not bitwise the same). */
+    int gpe_frozen;         /* condensate (ism_problem_create_gpe, n_grid 64 or 1024): 1 builds
+                               the boundaries of every iteration after the first by
+                               propagator assembling with the density frozen at the last
+                               slice pass's trajectories (the reading of Sec. 4.C): per slice
+                               the linear step maps S_j psi = Kh e^{-i tau (V(u_j)+g|a_j|^2)} Kh psi
+                               and the exact adjoint steps linearised at those a_j, assembled
+                               on basis vectors (n and 2n columns), then 2N matrix-vector
+                               products.  The iterates then differ from the plain gradient
+                               method's and share its fixed points; J^(k), F^(k) come from the
+                               assembled Psi_N.  Holds 3 B N n^2 complex doubles on the device
+                               from creation.  Default 0: exact sequential sweeps. */
 } ism_options;
 
 /* Fill *opt with the defaults listed above.  opt must not be NULL. */
@@ -148,11 +159,13 @@ int ism_problem_create(ism_problem** out, int d, int n_ctrl, const double* H0, c
  * Create a 1-D Gross-Pitaevskii problem (Sec. 4.C; step map Eq. (OS)):
  *   i d/dt psi = (-1/2 d_xx + V(x,u) + g |psi|^2) psi,   V(x,u) = V0(x) + u V1(x) + u^2 V2,
  * on the periodic grid x_m = -L/2 + m L/n_grid, with one scalar control (C = 1).
- *   n_grid  : 1024 or 4096 (power of two, LDS-resident FFT).
+ *   n_grid  : 64, 1024 or 4096 (LDS-resident FFT; 64 is the scale of the paper's own
+ *             50-point grid).
  *   L       : box length > 0.   g : nonlinearity.
  *   V0, V1  : n_grid doubles each.   V2 : scalar.
  *   psi0, target : n_grid complex, normalised with <a|b> = dx sum conj(a) b.
- *   T, K, N : as above.   opt : precision, batch, device, stream, io_device are used.
+ *   T, K, N : as above.   opt : precision, batch, device, stream, io_device and gpe_frozen
+ *             are used (gpe_frozen with n_grid 4096: ISM_E_UNSUPPORTED).
  */
 int ism_problem_create_gpe(ism_problem** out, int n_grid, double L, double g, const double* V0,
                            const double* V1, double V2, const double* psi0, const double* target,

@@ -46,7 +46,7 @@ class Options(ct.Structure):
                 ("h0_batched", ct.c_int), ("alpha", ct.POINTER(ct.c_double)),
                 ("alpha_len", ct.c_int), ("device", ct.c_int), ("stream", ct.c_void_p),
                 ("io_device", ct.c_int), ("alloc_async", ct.c_int), ("step_map", ct.c_int),
-                ("launch_per_pass", ct.c_int)]
+                ("launch_per_pass", ct.c_int), ("gpe_frozen", ct.c_int)]
 
 
 class Info(ct.Structure):
@@ -254,7 +254,7 @@ class Problem:
 
     @classmethod
     def create_gpe(cls, n, L_box, g, V0, V1, V2, psi0, target, T, K, N, precision="fp64",
-                   batch=1, device=0, stream=None, io_device=False):
+                   batch=1, device=0, stream=None, io_device=False, gpe_frozen=False):
         L = lib()
         V0 = np.ascontiguousarray(np.asarray(V0, dtype=np.float64))
         V1 = np.ascontiguousarray(np.asarray(V1, dtype=np.float64))
@@ -268,6 +268,7 @@ class Problem:
         tstream, stream = _handle_stream(stream, io_device, device)
         o.stream = stream
         o.io_device = 1 if io_device else 0
+        o.gpe_frozen = 1 if gpe_frozen else 0
         h = ct.c_void_p()
         _check(L.ism_problem_create_gpe(ct.byref(h), int(n), float(L_box), float(g), _cptr(V0),
                                         _cptr(V1), float(V2), _cptr(psi0), _cptr(target),
@@ -429,14 +430,15 @@ class Problem:
 
 
 def from_problem(prob, precision="fp64", N=None, batch=None, device=0, stream=None,
-                 io_device=False, set_u=True, step_map="exp", launch_per_pass=False):
+                 io_device=False, set_u=True, step_map="exp", launch_per_pass=False,
+                 gpe_frozen=False):
     """Create a handle from a ``problems.FiniteProblem`` (or ``problems.GpeProblem``)."""
     if hasattr(prob, "V0"):
         B = prob.batch if batch is None else batch
         p = Problem.create_gpe(prob.n, prob.L, prob.g, prob.V0, prob.V1, prob.V2, prob.psi0,
                                prob.target, prob.T, prob.K, prob.N if N is None else N,
                                precision=precision, batch=B, device=device, stream=stream,
-                               io_device=io_device)
+                               io_device=io_device, gpe_frozen=gpe_frozen)
         if set_u:
             p.set_controls(prob.u0[:B])
         return p

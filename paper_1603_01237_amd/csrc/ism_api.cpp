@@ -55,7 +55,7 @@ namespace ism {
 const char* const kKernelNames[KID_COUNT] = {
     "sp_params", "sp_assemble", "sp_boundary", "sp_slice", "check_finite",
     "gate_build", "gate_gemm", "gate_grad", "gate_boundary",
-    "gpe_sweep", "gpe_slice", "gpe_boundary", "sp_sweep", "err", "small_solve"};
+    "gpe_sweep", "gpe_slice", "gpe_boundary", "sp_sweep", "err", "small_solve", "gpe_assemble"};
 
 static hipEvent_t pool_get(ism_problem* p) {
     if (!p->event_pool.empty()) {
@@ -141,6 +141,7 @@ int common_setup(ism_problem* p, int d, int C, double T, int K, int N, const ism
     p->io_device = o->io_device;
     p->async_alloc = o->alloc_async != 0;
     p->launch_per_pass = o->launch_per_pass != 0;
+    p->gpe_frozen = o->gpe_frozen != 0;
     ISM_TRY_HIP(hipSetDevice(o->device));
     if (o->stream) {
         p->stream = (hipStream_t)o->stream;
@@ -509,6 +510,7 @@ void ism_default_options(ism_options* o) {
     o->alloc_async = 0;
     o->step_map = ISM_STEP_EXP;
     o->launch_per_pass = 0;
+    o->gpe_frozen = 0;
 }
 
 const char* ism_status_string(int s) {
@@ -744,8 +746,13 @@ int iterate_loop(ism_problem* p, int n_iter, int n_inner, double rho, double fid
             if (fills) ISM_TRY_HIP(launch_fill_i32(p->flags + 1, 0, 1, p->stream));
             else ISM_TRY_HIP(hipMemsetAsync(p->flags + 1, 0, sizeof(int), p->stream));
         }
-        // steps (a)-(b): boundaries and intermediate states at u^(k)
-        if ((st = boundary_pass(p, jbuf + (size_t)k * p->B, fid_stop, true))) return st;
+        // steps (a)-(b): boundaries and intermediate states at u^(k); the condensate's
+        // frozen-density mode assembles them from the last slice pass's trajectories
+        if (p->path == PATH_GPE && p->gpe_frozen && k > 0)
+            st = gpe_boundary_frozen_pass(p, jbuf + (size_t)k * p->B, fid_stop, true);
+        else
+            st = boundary_pass(p, jbuf + (size_t)k * p->B, fid_stop, true);
+        if (st) return st;
         if (check_stop) {
             int fl[4];
             if ((st = read_flags(p, fl))) return st;
@@ -878,7 +885,7 @@ size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kin
     const size_t B = batch, KC = (size_t)K * n_ctrl;
     const size_t rs = precision == ISM_FP64 ? 8 : 4;
     size_t bytes = B * KC * 8 * 2 + K * 8 + (N + 1) * 4 + B * 64;   // u, grad, alpha, s, J/F/flags
-    if (gpe_grid > 0) {
+    if (gpe_grid > 0) {      // (frozen-density mode: gpe_frozen_bytes more)
         const size_t n = gpe_grid;
         return bytes + 4 * n * 8 + 2 * n * 16 +
                gpe_footprint_extra(n, K, N, batch, precision);

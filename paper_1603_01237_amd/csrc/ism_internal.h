@@ -104,7 +104,7 @@ enum KernelId {
     KID_SP_PARAMS = 0, KID_SP_ASSEMBLE, KID_SP_BOUNDARY, KID_SP_SLICE, KID_CHECK,
     KID_GATE_BUILD, KID_GATE_GEMM, KID_GATE_GRAD, KID_GATE_BOUNDARY,
     KID_GPE_SWEEP, KID_GPE_SLICE, KID_GPE_BOUNDARY, KID_SP_SWEEP, KID_ERR, KID_SMALL_SOLVE,
-    KID_COUNT
+    KID_GPE_ASSEMBLE, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -186,6 +186,9 @@ struct ism_problem {
     ism::dcx* Lam = nullptr;
     ism::dcx* phi = nullptr;
     void* M = nullptr;
+
+    // condensate: boundaries of iterations after the first by frozen-density assembling
+    int gpe_frozen = 0;
 
     // one-launch solve of small FP64 state problems (k_small.hip)
     int launch_per_pass = 0;   // option: never use it

@@ -85,6 +85,9 @@ size_t gate_footprint_extra(int d, int C, int K, int N, int batch, int precision
 int gpe_create(ism_problem* p, int n_grid, double L, double g, const double* V0, const double* V1,
                double V2, const double* psi0, const double* target);
 int gpe_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active);
+// boundaries by frozen-density propagator assembling, densities of the last slice pass
+int gpe_boundary_frozen_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active);
+size_t gpe_frozen_bytes(size_t n, int N, int batch);
 int gpe_slice_pass(ism_problem* p, int update, double rho, double* grad, bool use_active);
 int gpe_copy_state(ism_problem* p, double* out, int which_end);
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision);

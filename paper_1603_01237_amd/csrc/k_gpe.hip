@@ -1,5 +1,5 @@
 // Gross-Pitaevskii path (Sec. 4.C): i d/dt psi = (-1/2 d_xx + V(x,u) + g|psi|^2) psi on a
-// periodic grid of n = 1024 or 4096 points, V(x,u) = V0(x) + u V1(x) + u^2 V2, one control.
+// periodic grid of n = 64, 1024 or 4096 points, V(x,u) = V0(x) + u V1(x) + u^2 V2, one control.
 //
 // Step map: Strang splitting (Eq. (OS)) with exact kinetic half steps in Fourier space,
 //   a_j = F^-1 Kh F psi_j,  b_j = e^{-i theta_j} a_j,  theta_j = tau (V(x,u_j) + g |a_j|^2),
@@ -22,7 +22,7 @@
 //
 // Data layout: a workgroup of n/16 threads holds the state in registers, thread t owning
 // the points t + (n/16) i, i = 0..15.  The FFT is a Stockham transform of radices
-// 16, 16, 16 (n = 4096) or 16, 16, 4 (n = 1024): the first pass reads its inputs from
+// 16, 16, 16 (n = 4096), 16, 16, 4 (n = 1024) or 16, 4 (n = 64): the first pass reads its inputs from
 // registers and the last pass leaves its outputs in registers in the same ownership
 // pattern, so the pointwise potential phase, the kinetic factors, the trajectory and the
 // gradient terms are formed in registers and only two exchanges per transform go through
@@ -169,6 +169,26 @@ __device__ void fft(Cd (&x)[16], const Lds& L) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) L.st(pad(16 * t + c), x[c]);
     __syncthreads();
+    if constexpr (NN == 64) {
+        // pass 2: radix 4 over the four 16-point sub-transforms, twiddle W_64^{q c}:
+        // thread t forms X[c + 16 q'] for c = t + 4 s, kept in x[s + 4 q'] (point
+        // t + 4 (s + 4 q'), the natural ownership)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int c = t + 4 * s4;
+            Cd v0 = L.ld(pad(c)), v1 = L.ld(pad(16 + c)), v2 = L.ld(pad(32 + c)),
+               v3 = L.ld(pad(48 + c));
+            v1 = cmul_s<SIGN>(v1, L.tab(512 + 16 + c));
+            v2 = cmul_s<SIGN>(v2, L.tab(512 + 32 + c));
+            v3 = cmul_s<SIGN>(v3, L.tab(512 + 48 + c));
+            dft4<SIGN>(v0, v1, v2, v3);
+            x[s4] = v0;
+            x[s4 + 4] = v1;
+            x[s4 + 8] = v2;
+            x[s4 + 12] = v3;
+        }
+        return;
+    }
     // pass 2: radix 16, sub-transform size 16
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = L.ld(pad(t + T * r));
@@ -191,7 +211,7 @@ __device__ void fft(Cd (&x)[16], const Lds& L) {
             x[r] = cmul_s<SIGN>(x[r], cmul(L.tab(256 + r * 16 + kh), L.tab(512 + r * 16 + kl)));
         dft16<SIGN>(x);
     } else {
-        static_assert(NN == 1024, "grid sizes 1024 and 4096");
+        static_assert(NN == 1024 || NN == 64, "grid sizes 64, 1024 and 4096");   // 64 returned above
         Cd y[16];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -267,9 +287,10 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, double (&v
 // deterministic workgroup sum (wave tree, then the wavefront partials in order)
 template <int NN>
 __device__ __forceinline__ double block_sum(double v, const Lds& L) {
+    constexpr int TT = NN / 16 < 64 ? NN / 16 : 64;        // lanes of the (first) wavefront
     constexpr int NW = NN / 16 / 64;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if constexpr (NW == 1) return v;
+    for (int off = TT / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, TT);
+    if constexpr (NW <= 1) return v;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -519,6 +540,142 @@ __global__ __launch_bounds__(NN / 16) void k_gpe_slice(GpeArgs A) {
     adj_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b, nullptr, 0, true, upd);
 }
 
+// ---------------------------------------------------------------------------------------
+// Frozen-density propagator assembling (the reading of Sec. 4.C's propagator assembling for
+// the condensate).  With a_j frozen at the last slice pass's trajectories (traj), one Strang
+// step is the linear unitary map S_j psi = Kh e^{-i tau (V(u_j) + g |a_j|^2)} Kh psi and the
+// exact adjoint step linearised there is the real-linear map R_j of adj_run.  The slice maps
+// are formed on basis vectors (one workgroup per vector, slice and instance), and the
+// boundaries follow from 2N matrix-vector products:
+//   Psi_0 = psi0, Psi_{n+1} = M_n Psi_n;  Lambda_N = psi_f,
+//   Lambda_n = sum_m Re(Lambda_{n+1,m}) A_n(e_m) + Im(Lambda_{n+1,m}) A_n(i e_m).
+// Column v of M_n (and of A_n) is stored contiguously: M[((b N + n) ncol + v) n_grid + r].
+
+// column v of M_n: S_{j1-1} ... S_{j0} e_v (kinetic half steps fused inside the slice)
+template <int NN, typename R>
+__global__ __launch_bounds__(NN / 16) void k_gpe_frozen_fwd(GpeArgs A, dcx* M) {
+    extern __shared__ unsigned char smem_raw[];
+    const Lds L = lds_carve<NN>(smem_raw);
+    const int v = blockIdx.x, nn = blockIdx.y, b = blockIdx.z;
+    constexpr int T = NN / 16;
+    const int t = threadIdx.x;
+    double v0[16], v1[16];
+    setup<NN>(A, L, v0, v1);
+    const int j0 = A.s[nn], j1 = A.s[nn + 1];
+    const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
+    const double* ub = A.u + (size_t)b * A.K;
+    Cd x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = Cd{t + T * i == v ? 1.0 : 0.0, 0.0};
+    kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
+    for (int j = j0; j < j1; ++j) {
+        const double u = ub[j];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const Cd af = up<R>(traj_b[(size_t)j * NN + t + T * i]);     // frozen a_j
+            x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, af));
+        }
+        kick<NN, false>(x, L, j + 1 < j1 ? nullptr : reinterpret_cast<const Cd*>(A.Kh));
+    }
+    store_state<NN>(M + (((size_t)b * A.N + nn) * NN + v) * NN, x);
+}
+
+// column c of A_n: R_{j0} ... R_{j1-1} applied to e_c (c < n) or i e_{c-n}
+template <int NN, typename R>
+__global__ __launch_bounds__(NN / 16) void k_gpe_frozen_adj(GpeArgs A, dcx* Aj) {
+    extern __shared__ unsigned char smem_raw[];
+    const Lds L = lds_carve<NN>(smem_raw);
+    const int c = blockIdx.x, nn = blockIdx.y, b = blockIdx.z;
+    constexpr int T = NN / 16;
+    const int t = threadIdx.x;
+    double v0[16], v1[16];
+    setup<NN>(A, L, v0, v1);
+    const int j0 = A.s[nn], j1 = A.s[nn + 1];
+    const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
+    const int m = c < NN ? c : c - NN;
+    Cd x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const bool on = t + T * i == m;
+        x[i] = c < NN ? Cd{on ? 1.0 : 0.0, 0.0} : Cd{0.0, on ? 1.0 : 0.0};
+    }
+    kick<NN, true>(x, L, reinterpret_cast<const Cd*>(A.Kh));
+    adj_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b,
+                   Aj + (((size_t)b * A.N + nn) * 2 * NN + c) * NN, 1, false, false);
+}
+
+// y = sum_c w_c col_c over ncol columns of n_grid entries (one thread per entry, instances on
+// blockIdx.y): complex weights w_c = x_c (ncol = n_grid), or real weights Re x_c, Im x_c
+// for the columns c and n_grid + c (ncol = 2 n_grid)
+__global__ __launch_bounds__(256) void k_gpe_gemv(const dcx* cols, size_t cstride, int ng,
+                                                  int realw, const dcx* x, size_t xstride,
+                                                  dcx* y, size_t ystride) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (r >= ng) return;
+    const dcx* C = cols + (size_t)b * cstride;
+    const dcx* xb = x + (size_t)b * xstride;
+    double ar = 0.0, ai = 0.0;
+    if (!realw) {
+        for (int c = 0; c < ng; ++c) {
+            const dcx m = C[(size_t)c * ng + r], w = xb[c];
+            ar = fma(m.re, w.re, fma(-m.im, w.im, ar));
+            ai = fma(m.re, w.im, fma(m.im, w.re, ai));
+        }
+    } else {
+        for (int c = 0; c < ng; ++c) {
+            const dcx m1 = C[(size_t)c * ng + r], m2 = C[(size_t)(ng + c) * ng + r];
+            const dcx w = xb[c];
+            ar = fma(m1.re, w.re, fma(m2.re, w.im, ar));
+            ai = fma(m1.im, w.re, fma(m2.im, w.im, ai));
+        }
+    }
+    y[(size_t)b * ystride + r] = dcx{ar, ai};
+}
+
+// Psi_0 = psi0 and Lambda_N = psi_f for every instance
+__global__ void k_gpe_bnd_ends(GpeArgs A) {
+    const int b = blockIdx.y;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < A.n; r += gridDim.x * blockDim.x) {
+        A.Psi[(size_t)b * (A.N + 1) * A.n + r] = A.psi0[r];
+        A.Lam[((size_t)b * (A.N + 1) + A.N) * A.n + r] = A.target[r];
+    }
+}
+
+// J, F from Psi_N (fixed-order reduction), freezing at fid_stop, numeric flag
+__global__ __launch_bounds__(256) void k_gpe_bnd_finish(GpeArgs A) {
+    __shared__ double rr[256], ri[256];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const dcx* P = A.Psi + ((size_t)b * (A.N + 1) + A.N) * A.n;
+    double zr = 0.0, zi = 0.0;
+    for (int r = t; r < A.n; r += 256) {
+        const dcx p = P[r], f = A.target[r];
+        zr += p.re * f.re + p.im * f.im;
+        zi += p.re * f.im - p.im * f.re;
+    }
+    rr[t] = zr;
+    ri[t] = zi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            rr[t] += rr[t + w];
+            ri[t] += ri[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double J = A.dx * rr[0], Zi = A.dx * ri[0];
+        const double F = J * J + Zi * Zi;
+        A.J[b] = J;
+        A.F[b] = F;
+        if (A.Jhist) A.Jhist[b] = J;
+        if (!(fabs(J) < 1e300)) atomicOr(&A.flags[0], 1);
+        if (A.active) {
+            if (A.active[b] && F >= A.fid_stop) A.active[b] = 0;
+            if (A.active[b]) atomicAdd(&A.flags[1], 1);
+        }
+    }
+}
+
 }  // namespace
 
 struct GpeExt {
@@ -535,6 +692,8 @@ struct GpeExt {
     dcx* psi0 = nullptr;
     dcx* target = nullptr;
     void* traj = nullptr;
+    dcx* fM = nullptr;     // frozen-density slice maps: B N n columns of n (forward)
+    dcx* fA = nullptr;     //                            B N 2n columns of n (adjoint)
 };
 
 static void gpe_free(ism_problem* p) {
@@ -545,6 +704,10 @@ static void gpe_free(ism_problem* p) {
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision) {
     const size_t rs = precision == ISM_FP64 ? 16 : 8;
     return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 2 + 768) * 16;
+}
+
+size_t gpe_frozen_bytes(size_t n, int N, int batch) {
+    return (size_t)batch * N * 3 * n * n * sizeof(dcx);
 }
 
 static GpeArgs gpe_args(ism_problem* p) {
@@ -584,36 +747,65 @@ static size_t gpe_shmem(int n) {
            2 * ((size_t)n / 2 + 1) * sizeof(double) + 16 * sizeof(double);
 }
 
+template <int NN, typename R>
+static void gpe_launch_sweeps_n(const GpeArgs& A, hipStream_t st, size_t shm) {
+    hipLaunchKernelGGL((k_gpe_fwd_sweep<NN, R>), dim3(A.B), dim3(NN / 16), shm, st, A);
+    hipLaunchKernelGGL((k_gpe_adj_sweep<NN, R>), dim3(A.B), dim3(NN / 16), shm, st, A);
+}
+
 template <typename R>
 static void gpe_launch_sweeps(const GpeArgs& A, hipStream_t st, size_t shm) {
-    if (A.n == 4096) {
-        hipLaunchKernelGGL((k_gpe_fwd_sweep<4096, R>), dim3(A.B), dim3(256), shm, st, A);
-        hipLaunchKernelGGL((k_gpe_adj_sweep<4096, R>), dim3(A.B), dim3(256), shm, st, A);
-    } else {
-        hipLaunchKernelGGL((k_gpe_fwd_sweep<1024, R>), dim3(A.B), dim3(64), shm, st, A);
-        hipLaunchKernelGGL((k_gpe_adj_sweep<1024, R>), dim3(A.B), dim3(64), shm, st, A);
-    }
+    if (A.n == 4096) gpe_launch_sweeps_n<4096, R>(A, st, shm);
+    else if (A.n == 1024) gpe_launch_sweeps_n<1024, R>(A, st, shm);
+    else gpe_launch_sweeps_n<64, R>(A, st, shm);
 }
 
 template <typename R>
 static void gpe_launch_slice(const GpeArgs& A, hipStream_t st, size_t shm) {
     if (A.n == 4096)
         hipLaunchKernelGGL((k_gpe_slice<4096, R>), dim3(A.N, A.B), dim3(256), shm, st, A);
-    else
+    else if (A.n == 1024)
         hipLaunchKernelGGL((k_gpe_slice<1024, R>), dim3(A.N, A.B), dim3(64), shm, st, A);
+    else
+        hipLaunchKernelGGL((k_gpe_slice<64, R>), dim3(A.N, A.B), dim3(4), shm, st, A);
 }
 
 template <int NN, typename R>
 static hipError_t gpe_set_shmem(int shm) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_gpe_fwd_sweep<NN, R>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, shm);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_gpe_adj_sweep<NN, R>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, shm);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_gpe_slice<NN, R>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+    const void* ks[] = {(const void*)k_gpe_fwd_sweep<NN, R>, (const void*)k_gpe_adj_sweep<NN, R>,
+                        (const void*)k_gpe_slice<NN, R>, (const void*)k_gpe_frozen_fwd<NN, R>,
+                        (const void*)k_gpe_frozen_adj<NN, R>};
+    hipError_t e = hipSuccess;
+    for (const void* k : ks)
+        if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, shm);
     return e;
+}
+
+// slice maps at the current controls with the densities of the last slice pass, then the
+// 2N boundary products, J and F
+template <int NN, typename R>
+static void gpe_launch_frozen(ism_problem* p, const GpeArgs& A, GpeExt* x, size_t shm) {
+    const int B = A.B, N = A.N;
+    {
+        TimeScope ts(p, KID_GPE_ASSEMBLE);
+        hipLaunchKernelGGL((k_gpe_frozen_fwd<NN, R>), dim3(NN, N, B), dim3(NN / 16), shm,
+                           p->stream, A, x->fM);
+        hipLaunchKernelGGL((k_gpe_frozen_adj<NN, R>), dim3(2 * NN, N, B), dim3(NN / 16), shm,
+                           p->stream, A, x->fA);
+    }
+    TimeScope ts(p, KID_GPE_BOUNDARY);
+    const dim3 g((NN + 255) / 256, B), blk(NN < 256 ? NN : 256);
+    const size_t nb = (size_t)(N + 1) * NN;
+    hipLaunchKernelGGL(k_gpe_bnd_ends, g, blk, 0, p->stream, A);
+    for (int n = 0; n < N; ++n)
+        hipLaunchKernelGGL(k_gpe_gemv, g, blk, 0, p->stream, x->fM + (size_t)n * NN * NN,
+                           (size_t)N * NN * NN, NN, 0, x->Psi + (size_t)n * NN, nb,
+                           x->Psi + (size_t)(n + 1) * NN, nb);
+    for (int n = N - 1; n >= 0; --n)
+        hipLaunchKernelGGL(k_gpe_gemv, g, blk, 0, p->stream, x->fA + (size_t)n * 2 * NN * NN,
+                           (size_t)N * 2 * NN * NN, NN, 1, x->Lam + (size_t)(n + 1) * NN, nb,
+                           x->Lam + (size_t)n * NN, nb);
+    hipLaunchKernelGGL(k_gpe_bnd_finish, dim3(B), dim3(256), 0, p->stream, A);
 }
 
 template <typename R>
@@ -645,6 +837,28 @@ static int gpe_slice_t(ism_problem* p, int update, double rho, double* grad, boo
     if (hipGetLastError() != hipSuccess) return ISM_E_DEVICE;
     if (update) p->bvalid = false;
     return ISM_OK;
+}
+
+template <typename R>
+static int gpe_boundary_frozen_t(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active) {
+    GpeExt* x = reinterpret_cast<GpeExt*>(p->ext);
+    if (!x->fM || !x->fA) return ISM_E_STATE;
+    GpeArgs A = gpe_args(p);
+    A.Jhist = Jhist_k;
+    A.active = use_active ? p->active : nullptr;
+    A.fid_stop = fid_stop;
+    const size_t shm = gpe_shmem(A.n);
+    if (A.n == 1024) gpe_launch_frozen<1024, R>(p, A, x, shm);
+    else gpe_launch_frozen<64, R>(p, A, x, shm);
+    if (hipGetLastError() != hipSuccess) return ISM_E_DEVICE;
+    p->bvalid = true;
+    return ISM_OK;
+}
+
+int gpe_boundary_frozen_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active) {
+    return p->precision == ISM_FP64
+               ? gpe_boundary_frozen_t<double>(p, Jhist_k, fid_stop, use_active)
+               : gpe_boundary_frozen_t<float>(p, Jhist_k, fid_stop, use_active);
 }
 
 int gpe_boundary_pass(ism_problem* p, double* Jhist_k, double fid_stop, bool use_active) {
@@ -723,12 +937,20 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
     if ((st = dev_alloc(p, (void**)&x->Psi, nb))) return st;
     if ((st = dev_alloc(p, (void**)&x->Lam, nb))) return st;
     if ((st = dev_alloc(p, &x->traj, (size_t)p->B * p->K * n * (f64 ? 16 : 8)))) return st;
+    if (p->gpe_frozen) {      // slice maps of the frozen-density boundaries, held from the start
+        if (n > 1024) return ISM_E_UNSUPPORTED;
+        const size_t m = (size_t)p->B * p->N * n * n * sizeof(dcx);
+        if ((st = dev_alloc(p, (void**)&x->fM, m))) return st;
+        if ((st = dev_alloc(p, (void**)&x->fA, 2 * m))) return st;
+    }
     const int shm = (int)gpe_shmem(n);
     hipError_t e;
     if (n == 4096)
         e = f64 ? gpe_set_shmem<4096, double>(shm) : gpe_set_shmem<4096, float>(shm);
-    else
+    else if (n == 1024)
         e = f64 ? gpe_set_shmem<1024, double>(shm) : gpe_set_shmem<1024, float>(shm);
+    else
+        e = f64 ? gpe_set_shmem<64, double>(shm) : gpe_set_shmem<64, float>(shm);
     if (e != hipSuccess) return ISM_E_DEVICE;
     return ISM_OK;
 }
@@ -746,7 +968,8 @@ extern "C" int ism_problem_create_gpe(ism_problem** out, int n_grid, double L, d
     if (opt) o = *opt;
     o.kind = ISM_STATE;
     if (o.step_map != ISM_STEP_EXP) return ISM_E_UNSUPPORTED;   // the condensate uses Eq. (OS)
-    if (n_grid != 1024 && n_grid != 4096) return n_grid > 0 ? ISM_E_UNSUPPORTED : ISM_E_ARG;
+    if (n_grid != 64 && n_grid != 1024 && n_grid != 4096)
+        return n_grid > 0 ? ISM_E_UNSUPPORTED : ISM_E_ARG;
     if (!(L > 0.0) || !std::isfinite(L) || !std::isfinite(g) || !std::isfinite(V2)) return ISM_E_ARG;
     int st = validate_common(n_grid, 1, T, K, N, &o);
     if (st) return st;

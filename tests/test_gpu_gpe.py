@@ -56,6 +56,9 @@ CASES = [
     ("n1024_g0_K25_N5", lambda: _small(K=25, N=5, g=0.0)),
     ("n1024_batch2", lambda: _small(K=20, N=3, batch=2)),
     ("n1024_K1_N1_single_step", lambda: _small(K=1, N=1, T=0.01)),
+    # the paper's own scale (a 50-point grid, here 64 points on [-10, 10])
+    ("n64_L20_K64_N8", lambda: _small(n=64, L=20.0, K=64, N=8, g=1.0, T=1.0)),
+    ("n64_L20_K37_N5_batch2", lambda: _small(n=64, L=20.0, K=37, N=5, g=1.0, T=0.6, batch=2)),
 ]
 
 
