@@ -72,7 +72,7 @@ def copy_calibration():
                                            "write_bytes": COPY_BYTES, "launches": 3}}), flush=True)
 
 
-def serving_sample(n_req, max_iter=20, iters_per_round=5, max_running=16):
+def serving_sample(n_req, max_iter=20, iters_per_round=5, max_running=16, shapes="continuous"):
     """Replay of the first n_req requests of the seeded 200 req/s serving trace at their
     arrival times (FP32 mixed; stop at F >= 0.99 or max_iter iterations).  The trace offers
     far more work than the device serves (200 requests arrive within about a second), so the
@@ -82,7 +82,7 @@ def serving_sample(n_req, max_iter=20, iters_per_round=5, max_running=16):
     import problems
     from paper_1603_01237_amd import Server
     from paper_1603_01237_amd.serve import latency_summary, replay
-    trace = problems.serving_trace()[:n_req]
+    trace = problems.serving_trace(shapes=shapes)[:n_req]
     types = [f"{r['type']}{r['size']}" for r in trace]
     items = [(r["arrival"] - trace[0]["arrival"], problems.request_problem(r),
               dict(max_iter=max_iter, rho=problems.SERVE_RHO[r["type"]], fid_stop=0.99,
@@ -101,15 +101,18 @@ def serving_sample(n_req, max_iter=20, iters_per_round=5, max_running=16):
     out.update({"sustainable_solves_per_s": out["solves_per_s"],
                 "offered_req_per_s": n_req / max(trace[-1]["arrival"] - trace[0]["arrival"], 1e-9),
                 "handles": st["groups"], "merged_requests": st["merged"],
-                "busy_frac": st["busy_s"] / wall if wall > 0 else None,
+                "request_in_flight_frac": st["busy_s"] / wall if wall > 0 else None,
                 "peak_device_GB": st["bytes_peak"] / 1e9,
                 "mean_iters": float(sum(r["iters"] for r in recs) / max(len(recs), 1)),
                 "reached_F099": int(sum(r["F"] >= 0.99 for r in recs)),
                 "sample": f"first {n_req} requests of the seeded 200 req/s trace (spin d in "
-                          "{4,16,64,256}, rotor j<=10/20/40, GPE n=1024/4096; K log-uniform "
-                          "1000..20000, N 16..128), arrival-time replay, FP32 mixed, stop at "
+                          "{4,16,64,256}, rotor j<=10/20/40, GPE n=1024/4096; " +
+                          ("K log-uniform 1000..20000, N 16..128" if shapes == "continuous" else
+                           "K in {1000,2000,5000,10000,20000}, N in {16,32,64,128}") +
+                          "), arrival-time replay, FP32 mixed, stop at "
                           f"F>=0.99 or {max_iter} iterations (the trace's 200 capped to keep the "
-                          "replay near a minute); busy_frac: time with a request running"})
+                          "replay near a minute); request_in_flight_frac: share of the wall "
+                          "time with at least one request running (not GPU utilisation)"})
     return out
 
 
@@ -225,6 +228,7 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2,
         out.update(_gate_workload(stream, iters_gate))
     if "gpe" in which:
         out.update(_gpe_workload(stream, iters_gpe))
+        out.update(_gpe_frozen_workload(stream))
     return out
 
 
@@ -313,9 +317,55 @@ def _density_workload(stream, steps=2):
     out["ms_per_iteration"]["fp64_N8"] = r["seconds"] / steps * 1e3
     out["kernels_ms_per_iteration"]["fp64_N8"] = {n: t[1] / steps for n, t in r["kernels"].items()}
     t = out["ms_per_iteration"]
-    out["efficiency_fp32"] = {f"N{N}": t["fp32_N1"] / (N * t[f"fp32_N{N}"]) for N in (1, 2, 4, 8)}
+    # t(1) / (N t(N)): the paper's parallel efficiency, which on one GPU measures how the
+    # slicing changes the per-iteration time (the chunked scans make it flat in N), not the
+    # use of N processors
+    out["slicing_time_ratio_fp32"] = {f"N{N}": t["fp32_N1"] / (N * t[f"fp32_N{N}"])
+                                      for N in (1, 2, 4, 8)}
     out["useful_matrix_steps_per_s"] = {k: 2 * p.K / (v * 1e-3) for k, v in t.items()}
     return {"spin5_density": out}
+
+
+def _gpe_frozen_workload(stream, iters=40, target=0.998):
+    """The condensate at the paper's scale (64 grid points on [-10, 10], 2^9 steps, T = 8,
+    g = 1, rho = 0.1; the moving-trap stand-in for Sec. 4.C's double well): iterations and time
+    to reach J >= target with the frozen-density boundaries (B16) for N = 1..32 slices, and
+    with the exact sweeps (the plain gradient method's iterates).  The counterpart of Table
+    tabGP: iterations(N = 1) / iterations(N), and the wall time to the target against the
+    sequential method."""
+    import numpy as np
+    import problems
+    from paper_1603_01237_amd import _lib
+    base = problems.gpe(n=64, L=20.0, g=1.0, dt=8.0 / 512, K=512, N=1, x_target=3.0)
+    out = {"workload": "condensate, n=64 on [-10,10], K=512, T=8, g=1, rho=0.1, FP64; "
+                       f"iterations to J >= {target}",
+           "frozen": {}, "exact": {}}
+    for frozen in (True, False):
+        for N in (1, 2, 4, 8, 16, 32):
+            with _lib.from_problem(base, precision="fp64", N=N, stream=stream,
+                                   gpe_frozen=frozen) as h:
+                t0 = time.perf_counter()
+                Jh, done = h.iterate(iters, 0.1)
+                dt = time.perf_counter() - t0
+            J = Jh[:, 0]
+            hit = np.nonzero(J >= target)[0]
+            key = "frozen" if frozen else "exact"
+            out[key][f"N{N}"] = {"iterations": int(hit[0]) if hit.size else None,
+                                 "ms_per_iteration": dt / iters * 1e3,
+                                 "J_final": float(J[-1])}
+    for key in ("frozen", "exact"):
+        for v in out[key].values():
+            v["ms_to_target"] = (v["iterations"] * v["ms_per_iteration"]
+                                 if v["iterations"] is not None else None)
+    it1 = out["frozen"]["N1"]["iterations"]
+    out["iteration_ratio_frozen"] = {k: (it1 / v["iterations"] if it1 and v["iterations"] else None)
+                                     for k, v in out["frozen"].items()}
+    # wall time to the target against the sequential method (exact sweeps, N = 1) on the
+    # same GPU: what the assembled boundaries buy here
+    t1 = out["exact"]["N1"]["ms_to_target"]
+    out["speedup_vs_sequential"] = {k: (t1 / v["ms_to_target"] if t1 and v["ms_to_target"] else None)
+                                    for k, v in out["frozen"].items()}
+    return {"gpe_frozen_n64": out}
 
 
 def _density_cn_workload(stream, steps=2):
@@ -687,6 +737,8 @@ def main():
         out["workloads"] = other_workloads(stream)
     if args.serve > 0:
         out["serving"] = serving_sample(args.serve)
+        # the same replay with requests in a few standard shapes, which the server merges
+        out["serving_standard_shapes"] = serving_sample(args.serve, shapes="standard")
     print(json.dumps(out), flush=True)
 
 

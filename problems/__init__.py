@@ -366,18 +366,29 @@ def gpe(seed: int = 1003, n: int = 4096, L: float = 40.0, g: float = 10.0, dt: f
 # serving trace
 # ----------------------------------------------------------------------------
 
-def serving_trace(seed: int = 1004, n_req: int = 2000, rate: float = 200.0):
+SERVE_STANDARD_K = (1000, 2000, 5000, 10000, 20000)
+SERVE_STANDARD_N = (16, 32, 64, 128)
+
+
+def serving_trace(seed: int = 1004, n_req: int = 2000, rate: float = 200.0,
+                  shapes: str = "continuous"):
     """Poisson arrivals (exponential gaps, mean 1/rate) of solve requests with a seeded
     type and size: spin chains d in {4,16,64,256}, rotors jmax in {10,20,40},
-    GPE grids {1024, 4096}; N uniform in [16,128]; K log-uniform in [1000, 20000]."""
+    GPE grids {1024, 4096}.  shapes = "continuous": N uniform in [16,128], K log-uniform in
+    [1000, 20000]; "standard": N and K drawn from the standard shapes SERVE_STANDARD_N and
+    SERVE_STANDARD_K (requests of one type, size and shape can share a batched launch)."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for i in range(n_req):
         t += rng.exponential(1.0 / rate)
         typ = ["spin", "rotor", "gpe"][rng.integers(0, 3)]
-        N = int(rng.integers(16, 129))
-        K = int(round(math.exp(rng.uniform(math.log(1000), math.log(20000)))))
+        if shapes == "standard":
+            N = int(SERVE_STANDARD_N[rng.integers(0, len(SERVE_STANDARD_N))])
+            K = int(SERVE_STANDARD_K[rng.integers(0, len(SERVE_STANDARD_K))])
+        else:
+            N = int(rng.integers(16, 129))
+            K = int(round(math.exp(rng.uniform(math.log(1000), math.log(20000)))))
         K = max(K, N)
         if typ == "spin":
             size = int([4, 16, 64, 256][rng.integers(0, 4)])
