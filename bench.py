@@ -209,7 +209,8 @@ def gpe_sweep_flops(prob):
 
 
 def other_workloads(stream, iters_gate=2, iters_gpe=2,
-                    which=("spins", "gate", "gpe", "rotor_cn", "rotor_inner", "density")):
+                    which=("spins", "gate", "gpe", "rotor_cn", "rotor_inner", "rotor_newton",
+                           "density")):
     """The paper's other benchmark shapes: the two-spin solve (latency), gate synthesis
     on MFMA, the condensate (sequential FFT sweeps), and the rotor batch with the
     Crank-Nicolson step map and with several gradient steps per slice problem."""
@@ -219,6 +220,8 @@ def other_workloads(stream, iters_gate=2, iters_gpe=2,
         out.update(_rotor_cn_workload(stream))
     if "rotor_inner" in which:
         out.update(_rotor_inner_workload(stream))
+    if "rotor_newton" in which:
+        out.update(_rotor_newton_workload(stream))
     if "density" in which:
         out.update(_density_workload(stream))
         out.update(_density_cn_workload(stream))
@@ -366,6 +369,29 @@ def _gpe_frozen_workload(stream, iters=40, target=0.998):
     out["speedup_vs_sequential"] = {k: (t1 / v["ms_to_target"] if t1 and v["ms_to_target"] else None)
                                     for k, v in out["frozen"].items()}
     return {"gpe_frozen_n64": out}
+
+
+def _rotor_newton_workload(stream, iters=8, m=10, eps=1e-4, batch=16):
+    """Newton-GMRES slice solver (Sec. 4.B, Table tabnewt) on the benchmark's rotors
+    (first `batch` instances, K = 20000, FP64): J after each of `iters` iterations for
+    N = 1, 2, 4, ..., 128, time per iteration, and N t per iteration (the paper's
+    equivalent sequential time per iteration)."""
+    import numpy as np
+    import problems
+    from paper_1603_01237_amd import _lib
+    out = {"workload": f"rotor batch, first {batch} instances, d=21, K=20000, FP64, one "
+                       f"Newton step per slice, GMRES m={m}, eps={eps}", "by_N": {}}
+    for N in (1, 2, 4, 8, 16, 32, 64, 128):
+        p = problems.rotor(batch=batch, N=N)
+        with _lib.from_problem(p, precision="fp64", stream=stream) as h:
+            t0 = time.perf_counter()
+            Jh, done = h.iterate_newton(iters, m, fd_eps=eps)
+            dt = time.perf_counter() - t0
+        J = Jh.mean(axis=1)
+        out["by_N"][f"N{N}"] = {"J_mean_per_iteration": [float(x) for x in J],
+                                "ms_per_iteration": dt / max(done, 1) * 1e3,
+                                "N_times_ms_per_iteration": N * dt / max(done, 1) * 1e3}
+    return {"rotor_newton": out}
 
 
 def _density_cn_workload(stream, steps=2):
@@ -653,7 +679,8 @@ def main():
                     help="skip the two-spin, gate and condensate workloads")
     ap.add_argument("--serve", type=int, default=200,
                     help="requests of the serving trace replayed for p50/p99 latency (0: skip)")
-    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn", "rotor_inner", "density"],
+    ap.add_argument("--only", choices=["spins", "gate", "gpe", "rotor_cn", "rotor_inner",
+                                       "rotor_newton", "density"],
                     help="run only this secondary workload and print its figures (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the streaming kernel that scales the HBM byte counters")
