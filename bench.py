@@ -36,9 +36,9 @@ PEAK_ALU = 78.6e12       # non-packed FP32 and FP64 vector FMA rate: 256 CU x 64
 # change to them the field is reported as null until the counters are taken again.
 TRAFFIC_SOURCES = ["paper_1603_01237_amd/csrc/k_sparse.hip",
                    "paper_1603_01237_amd/csrc/ism_internal.h"]
-TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 32519.5, "write_kib": 113344.0,
+TRAFFIC = {"kernel": "sp_assemble", "fetch_kib": 32510.6, "write_kib": 113344.0,
            "copy_fetch_per_kib": 0.50001, "copy_write_per_kib": 1.0,
-           "sha256": "895f0bf93f8f6e3cacbc2632cd97d78510082814c2c5c20d386b35d4b9ac77d5"}
+           "sha256": "a7f33726d8de546ffff7f29bd1c3bd2e0ba0dfb61bfbb04a6381a599c3fcc8b0"}
 COPY_BYTES = 1 << 30
 
 
