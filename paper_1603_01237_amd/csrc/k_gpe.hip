@@ -20,19 +20,26 @@
 // no slice propagator exists to assemble).  The slice gradient equals the plain gradient
 // on the slice (weight 1).
 //
-// Data layout: a workgroup of n/16 threads holds the state in registers, thread t owning
-// the points t + (n/16) i, i = 0..15.  The FFT is a Stockham transform of radices
-// 16, 16, 16 (n = 4096), 16, 16, 4 (n = 1024) or 16, 4 (n = 64): the first pass reads its inputs from
-// registers and the last pass leaves its outputs in registers in the same ownership
-// pattern, so the pointwise potential phase, the kinetic factors, the trajectory and the
-// gradient terms are formed in registers and only two exchanges per transform go through
-// one in-place LDS buffer (padded by one element per 16, which makes every access
-// pattern of the three passes bank-conflict free).  Butterflies, twiddles and the LDS
-// state are FP64 in both precisions; the FP32 mixed path stores the trajectory a_j and
-// forms the phase e^{-i theta} in FP32.
+// Data layout: a workgroup of T = n/P threads holds the state in registers, thread t
+// owning the points t + T i, i = 0..P-1.  The FFT is a Stockham transform whose first pass
+// reads its inputs from registers and whose last pass leaves its outputs in registers in the
+// same ownership pattern, so the pointwise potential phase, the kinetic factors, the
+// trajectory and the gradient terms are formed in registers and only the exchanges between
+// passes go through LDS (split real and imaginary planes of 8-byte words).
+//  * n = 4096: P = 8, 512 threads (two wavefronts per SIMD), radices 8, 8, 8, 8.  The
+//    per-lane twiddles of the three twiddled passes and the kinetic factors at the owned
+//    frequencies stay in registers for the whole launch; the three exchanges of a transform
+//    alternate between two LDS buffers, so each needs one barrier (a buffer is written
+//    again only after the barrier that follows its last reads), and an XOR swizzle of the
+//    word index makes every access pattern bank-conflict free.
+//  * n = 1024 and 64: P = 16, radices 16, 16, 4 and 16, 4, with one in-place buffer padded
+//    by one element per 16 and the kinetic factors and twiddles in LDS tables.
+// Butterflies, twiddles and the LDS state are FP64 in both precisions; the FP32 mixed path
+// stores the trajectory a_j and forms the phase e^{-i theta} in FP32.
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "ism_paths.h"
@@ -42,6 +49,20 @@ namespace {
 
 template <typename R> struct Cx { R re, im; };
 using Cd = Cx<double>;
+
+// points per thread and threads per workgroup of the FFT engine for grid size NN
+template <int NN> struct Lay {
+    static constexpr int P = NN == 4096 ? 8 : 16;
+    static constexpr int T = NN / P;
+};
+
+// Workgroup barrier that orders LDS only: the FFT exchanges go through LDS alone, and a
+// full barrier would also wait for the trajectory stores and read-ahead loads in flight.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ Cd cmul(Cd a, Cd b) {
     return Cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -117,12 +138,47 @@ __device__ __forceinline__ void dft16(Cd (&x)[16]) {
     for (int i = 0; i < 16; ++i) x[i] = y[i];
 }
 
+// 8-point DFT in place (x[c] <- sum_r x[r] e^{SIGN 2 pi i r c/8}): 4-point DFTs of the even
+// and odd inputs, then x[c] = E_c + W^c O_c, x[c+4] = E_c - W^c O_c with W = e^{SIGN 2 pi i/8}
+template <int SIGN>
+__device__ __forceinline__ void dft8(Cd (&x)[8]) {
+    dft4<SIGN>(x[0], x[2], x[4], x[6]);           // E_0..E_3
+    dft4<SIGN>(x[1], x[3], x[5], x[7]);           // O_0..O_3
+    constexpr double h = 0.70710678118654752440;  // cos(pi/4)
+    const Cd o0 = x[1];
+    const Cd o1{h * (x[3].re - SIGN * x[3].im), h * (x[3].im + SIGN * x[3].re)};
+    const Cd o2{-SIGN * x[5].im, SIGN * x[5].re};
+    const Cd o3{h * (-x[7].re - SIGN * x[7].im), h * (-x[7].im + SIGN * x[7].re)};
+    const Cd e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+    x[0] = Cd{e0.re + o0.re, e0.im + o0.im};
+    x[4] = Cd{e0.re - o0.re, e0.im - o0.im};
+    x[1] = Cd{e1.re + o1.re, e1.im + o1.im};
+    x[5] = Cd{e1.re - o1.re, e1.im - o1.im};
+    x[2] = Cd{e2.re + o2.re, e2.im + o2.im};
+    x[6] = Cd{e2.re - o2.re, e2.im - o2.im};
+    x[3] = Cd{e3.re + o3.re, e3.im + o3.im};
+    x[7] = Cd{e3.re - o3.re, e3.im - o3.im};
+}
+
+// word of element i in a plane of the radix-8 exchange buffers: one word of padding per 8.
+// Every access of an exchange is then a per-thread base plus a compile-time offset (writes
+// 8t + c -> 9t + c; 64 (t >> 3) + 8c + (t & 7) -> 72 (t >> 3) + (t & 7) + 9c;
+// 512 (t >> 6) + 64c + (t & 63) -> pad(512 (t >> 6) + (t & 63)) + 72c; reads t + 512 r ->
+// pad(t) + 576 r), so no address register is held per access; within 16 consecutive lanes
+// the writes of passes 0 and 1 fall on distinct 8-byte bank pairs, and the reads and the
+// writes of pass 2 on 15 distinct pairs (one pair shared by two lanes).
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+
 // LDS carve-up of a workgroup.  Complex arrays are split into real and imaginary planes of
 // doubles: the exchange accesses are then 8-byte words on consecutive (padded) addresses,
 // which the LDS serves without bank conflicts (interleaved pairs put lanes 16 bytes apart).
 struct Lds {
-    double* sr;        // n + n/16: padded FFT exchange buffer, real plane
-    double* si;        //           imaginary plane
+    double* sr;        // P = 16: n + n/16, padded FFT exchange buffer, real plane;
+    double* si;        //         imaginary plane.  P = 8: exchange buffer 0 (n each)
+    double* sr1;       // P = 8: exchange buffer 1
+    double* si1;
+    double* wr;        // P = 8: twiddles of passes 1 and 2, [r-1][k]: W_64^{r k} at
+    double* wi;        //        (r-1) 8 + k (k < 8), then W_512^{r k} at 56 + (r-1) 64 + k
     double* kr;        // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| = 0..n/2, rounded
     double* ki;
     double* klr;       // n/2 + 1: its rounding residual (exact factor = kr + klr)
@@ -142,8 +198,19 @@ struct Lds {
 
 template <int NN>
 __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
+    Lds L{};
+    if constexpr (Lay<NN>::P == 8) {
+        constexpr int PN = NN + NN / 8;
+        L.sr = reinterpret_cast<double*>(raw);
+        L.si = L.sr + PN;
+        L.sr1 = L.si + PN;
+        L.si1 = L.sr1 + PN;
+        L.wr = L.si1 + PN;
+        L.wi = L.wr + 504;
+        L.red = L.wi + 504;
+        return L;
+    }
     constexpr int PN = NN + NN / 16;
-    Lds L;
     L.sr = reinterpret_cast<double*>(raw);
     L.si = L.sr + PN;
     constexpr int KH = NN / 2 + 1;
@@ -157,10 +224,90 @@ __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
     return L;
 }
 
-// FFT of the register-resident state (natural order, thread t owns t + (NN/16) i), result
-// in the same layout.  SIGN = -1 forward e^{-2 pi i jk/n}; +1 inverse without 1/n.
+// Per-lane constants of the radix-8 engine (n = 4096, thread t), loaded once per launch:
+//   tw[r-1] = W_4096^{r t}, the twiddles of pass 3 (r = 1..7; passes 1 and 2 read theirs
+//   from an LDS table);
+//   kf[c] + kl[c] = e^{-i tau k^2/2} / n at the owned frequency t + 512 c (rounded value and
+//   its rounding residual, the residual kept in FP32).
+struct Eng8 {
+    Cd tw[7];
+    Cd kf[8];
+    Cx<float> kl[8];
+};
+struct Eng16 {};
+template <int NN>
+using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8, Eng16>;
+
+// one exchange of the radix-8 engine: element i of the plane pair (re, im)
+__device__ __forceinline__ void st8(double* re, double* im, int i, Cd v) {
+    re[pad8(i)] = v.re;
+    im[pad8(i)] = v.im;
+}
+__device__ __forceinline__ Cd ld8(const double* re, const double* im, int i) {
+    return Cd{re[pad8(i)], im[pad8(i)]};
+}
+
+// Radix-8 Stockham pass p = 1, 2, 3 over sub-transforms of size S = 8^p: thread t reads
+// x_r = A[t + 512 r], multiplies by W_{8S}^{r (t mod S)} and forms the 8-point DFT; passes 1
+// and 2 write y_c to B[8S (t / S) + S c + (t mod S)], pass 3 keeps X[t + 512 c] = y_c.
+template <int SIGN, int PASS>
+__device__ __forceinline__ void pass8(Cd (&x)[8], const double* ar, const double* ai,
+                                      double* br, double* bi, const Lds& L, const Eng8& E) {
+    const int t = threadIdx.x;
+    const double* pr = ar + pad8(t);
+    const double* pi = ai + pad8(t);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = Cd{pr[576 * r], pi[576 * r]};
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+        Cd w;
+        if constexpr (PASS == 1) w = Cd{L.wr[(r - 1) * 8 + (t & 7)], L.wi[(r - 1) * 8 + (t & 7)]};
+        else if constexpr (PASS == 2)
+            w = Cd{L.wr[56 + (r - 1) * 64 + (t & 63)], L.wi[56 + (r - 1) * 64 + (t & 63)]};
+        else w = E.tw[r - 1];
+        x[r] = cmul_s<SIGN>(x[r], w);
+    }
+    dft8<SIGN>(x);
+    if constexpr (PASS < 3) {
+        constexpr int S = PASS == 1 ? 8 : 64;
+        const int base = pad8((t / S) * 8 * S + (t & (S - 1)));
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {        // pad8(base + S c) = pad8(base) + (9 S / 8) c
+            br[base + (9 * S / 8) * c] = x[c].re;
+            bi[base + (9 * S / 8) * c] = x[c].im;
+        }
+    }
+}
+
+// radix-8 engine (n = 4096): forward transforms exchange through buffers 0, 1, 0 and
+// inverse ones through 1, 0, 1; they only occur in forward-inverse pairs, so consecutive
+// exchanges always alternate.  `hook` runs after the last exchange, before the last pass:
+// loads issued there have that pass to arrive in.
+template <int SIGN, typename Hook>
+__device__ __forceinline__ void fft8e(Cd (&x)[8], const Lds& L, const Eng8& E, Hook&& hook) {
+    double* ar = SIGN < 0 ? L.sr : L.sr1;
+    double* ai = SIGN < 0 ? L.si : L.si1;
+    double* br = SIGN < 0 ? L.sr1 : L.sr;
+    double* bi = SIGN < 0 ? L.si1 : L.si;
+    const int t = threadIdx.x;
+    dft8<SIGN>(x);                               // pass 0: sub-transform size 1
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {                // pad8(8t + c) = 9t + c
+        ar[9 * t + c] = x[c].re;
+        ai[9 * t + c] = x[c].im;
+    }
+    lds_sync();
+    pass8<SIGN, 1>(x, ar, ai, br, bi, L, E);
+    lds_sync();
+    pass8<SIGN, 2>(x, br, bi, ar, ai, L, E);
+    lds_sync();
+    hook();
+    pass8<SIGN, 3>(x, ar, ai, nullptr, nullptr, L, E);
+}
+
+// radix-16 engine (n = 1024, 64)
 template <int NN, int SIGN>
-__device__ void fft(Cd (&x)[16], const Lds& L) {
+__device__ void fft16e(Cd (&x)[16], const Lds& L) {
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
     // pass 1: radix 16, sub-transform size 1 (no twiddles)
@@ -201,17 +348,10 @@ __device__ void fft(Cd (&x)[16], const Lds& L) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) L.st(pad(base + 16 * c), x[c]);
     __syncthreads();
-    // pass 3: sub-transform size 256; twiddle W_n^{r k} = W_n^{16 r (k>>4)} W_n^{r (k&15)}
-    if constexpr (NN == 4096) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = L.ld(pad(t + 256 * r));
-        const int kh = t >> 4, kl = t & 15;
-#pragma unroll
-        for (int r = 1; r < 16; ++r)
-            x[r] = cmul_s<SIGN>(x[r], cmul(L.tab(256 + r * 16 + kh), L.tab(512 + r * 16 + kl)));
-        dft16<SIGN>(x);
-    } else {
-        static_assert(NN == 1024 || NN == 64, "grid sizes 64, 1024 and 4096");   // 64 returned above
+    // pass 3 (n = 1024): radix 4 over sub-transforms of size 256; twiddle
+    // W_n^{r k} = W_n^{16 r (k>>4)} W_n^{r (k&15)}
+    {
+        static_assert(NN == 1024 || NN == 64, "radix-16 engine: grid sizes 64 and 1024");
         Cd y[16];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -232,6 +372,23 @@ __device__ void fft(Cd (&x)[16], const Lds& L) {
     }
 }
 
+// FFT of the register-resident state (natural order, thread t owns t + T i), result in the
+// same layout.  SIGN = -1 forward e^{-2 pi i jk/n}; +1 inverse without 1/n.
+template <int NN, int SIGN, typename Hook>
+__device__ __forceinline__ void fft(Cd (&x)[Lay<NN>::P], const Lds& L, const Eng<NN>& E,
+                                    Hook&& hook) {
+    if constexpr (Lay<NN>::P == 8) {
+        fft8e<SIGN>(x, L, E, hook);
+    } else {
+        fft16e<NN, SIGN>(x, L);
+        hook();
+    }
+}
+
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 struct GpeArgs {
     int B, n, K, N;
     const int* s;
@@ -239,7 +396,8 @@ struct GpeArgs {
     const double* V0;
     const double* V1;
     double V2;
-    const dcx* tab;        // 768 FFT twiddles (FP64), layout of Lds::tab
+    const dcx* tab;        // FFT twiddles (FP64): n = 4096, W_4096^m for m = 0..4095;
+                           // otherwise the 768 entries of Lds::tab
     const dcx* Kh;         // n: e^{-i tau k^2/4} / n (FP64)
     const dcx* Kf;         // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| 0..n/2 (FP64)
     const dcx* Kfl;        // n/2 + 1: rounding residual of Kf (FP64)
@@ -260,10 +418,9 @@ struct GpeArgs {
     int update;
 };
 
-// tables into LDS, potentials into registers
+// kinetic factors and twiddles of the radix-16 engine into LDS
 template <int NN>
-__device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, double (&v0)[16],
-                                      double (&v1)[16]) {
+__device__ __forceinline__ void setup_tables(const GpeArgs& A, const Lds& L) {
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
     for (int i = t; i <= NN / 2; i += T) {
@@ -276,19 +433,53 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, double (&v
         L.tr[i] = A.tab[i].re;
         L.ti[i] = A.tab[i].im;
     }
+    __syncthreads();
+}
+
+// engine constants into registers (P = 8) or tables into LDS (P = 16); potentials into
+// registers
+template <int NN>
+__device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E,
+                                      double (&v0)[Lay<NN>::P], double (&v1)[Lay<NN>::P]) {
+    constexpr int T = Lay<NN>::T, P = Lay<NN>::P;
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < P; ++i) {
         v0[i] = A.V0[t + T * i];
         v1[i] = A.V1[t + T * i];
     }
-    __syncthreads();
+    if constexpr (P == 8) {
+        // W_64^{r k} = W_4096^{64 r k}, W_512^{r k} = W_4096^{8 r k}
+        for (int i = t; i < 504; i += T) {
+            const int m = i < 56 ? 64 * (i / 8 + 1) * (i & 7) : 8 * ((i - 56) / 64 + 1) * ((i - 56) & 63);
+            L.wr[i] = A.tab[m].re;
+            L.wi[i] = A.tab[m].im;
+        }
+#pragma unroll
+        for (int r = 1; r < 8; ++r) {
+            const dcx w = A.tab[(r * t) & (NN - 1)];
+            E.tw[r - 1] = Cd{w.re, w.im};
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int m = t + T * c, mf = m <= NN / 2 ? m : NN - m;
+            const dcx k = A.Kf[mf], kl = A.Kfl[mf];
+            E.kf[c] = Cd{k.re, k.im};
+            E.kl[c] = Cx<float>{(float)kl.re, (float)kl.im};
+        }
+        __syncthreads();
+        return;
+    } else {
+        setup_tables<NN>(A, L);
+    }
 }
 
 // deterministic workgroup sum (wave tree, then the wavefront partials in order)
 template <int NN>
 __device__ __forceinline__ double block_sum(double v, const Lds& L) {
-    constexpr int TT = NN / 16 < 64 ? NN / 16 : 64;        // lanes of the (first) wavefront
-    constexpr int NW = NN / 16 / 64;
+    constexpr int T = Lay<NN>::T;
+    constexpr int TT = T < 64 ? T : 64;                    // lanes of the (first) wavefront
+    constexpr int NW = T / 64;
     for (int off = TT / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, TT);
     if constexpr (NW <= 1) return v;
     __syncthreads();
@@ -306,19 +497,27 @@ __device__ __forceinline__ double block_sum(double v, const Lds& L) {
 // makes the same relative error at every one of the K steps of a sweep, which adds up
 // coherently (about 5e-13 over 10^4 steps).  The factor depends on |frequency| only, so the
 // LDS holds the frequencies 0..n/2.
-template <int NN, bool CONJ>
-__device__ __forceinline__ void kick(Cd (&x)[16], const Lds& L, const Cd* kt) {
-    constexpr int T = NN / 16;
-    fft<NN, -1>(x, L);
+template <int NN, bool CONJ, typename Hook>
+__device__ __forceinline__ void kick(Cd (&x)[Lay<NN>::P], const Lds& L, const Eng<NN>& E,
+                                     const Cd* kt, Hook&& hook) {
+    constexpr int T = Lay<NN>::T, P = Lay<NN>::P;
+    fft<NN, -1>(x, L, E, NoHook{});
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < P; ++i) {
         const int m = threadIdx.x + T * i;
         if (kt) {
             const Cd k = kt[m];
             x[i] = CONJ ? cmulc(x[i], k) : cmul(x[i], k);
         } else {
             const int mf = m <= NN / 2 ? m : NN - m;
-            const Cd k = L.kf(mf), kl = L.kfl(mf);
+            Cd k, kl;
+            if constexpr (P == 8) {
+                k = E.kf[i];
+                kl = up<float>(E.kl[i]);
+            } else {
+                k = L.kf(mf);
+                kl = L.kfl(mf);
+            }
             const Cd lo = CONJ ? cmulc(x[i], kl) : cmul(x[i], kl);
             const Cd v = x[i];
             if (CONJ)
@@ -329,24 +528,29 @@ __device__ __forceinline__ void kick(Cd (&x)[16], const Lds& L, const Cd* kt) {
                           fma(v.im, k.re, fma(v.re, k.im, lo.im))};
         }
     }
-    fft<NN, 1>(x, L);
+    fft<NN, 1>(x, L, E, hook);
+}
+template <int NN, bool CONJ>
+__device__ __forceinline__ void kick(Cd (&x)[Lay<NN>::P], const Lds& L, const Eng<NN>& E,
+                                     const Cd* kt) {
+    kick<NN, CONJ>(x, L, E, kt, NoHook{});
 }
 
 template <int NN>
-__device__ __forceinline__ void load_state(Cd (&x)[16], const dcx* src) {
-    constexpr int T = NN / 16;
+__device__ __forceinline__ void load_state(Cd (&x)[Lay<NN>::P], const dcx* src) {
+    constexpr int T = Lay<NN>::T;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < Lay<NN>::P; ++i) {
         const dcx v = src[threadIdx.x + T * i];
         x[i] = Cd{v.re, v.im};
     }
 }
 
 template <int NN>
-__device__ __forceinline__ void store_state(dcx* dst, const Cd (&x)[16]) {
-    constexpr int T = NN / 16;
+__device__ __forceinline__ void store_state(dcx* dst, const Cd (&x)[Lay<NN>::P]) {
+    constexpr int T = Lay<NN>::T;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[threadIdx.x + T * i] = dcx{x[i].re, x[i].im};
+    for (int i = 0; i < Lay<NN>::P; ++i) dst[threadIdx.x + T * i] = dcx{x[i].re, x[i].im};
 }
 
 // e^{-i theta} at the owned points, theta = tau (V(x,u) + g |a|^2) (V in FP64)
@@ -359,33 +563,59 @@ __device__ __forceinline__ Cd phase(const GpeArgs& A, double v0, double v1, doub
     return Cd{(double)cs, -(double)sn};
 }
 
+// The radix-8 engine has no registers to spare for the potentials across a transform: they
+// are loaded again inside the last pass of every inverse transform (`reload_pot`, called
+// from the kick's hook), through a pointer the compiler cannot prove unchanged, so the loads
+// stay where they are issued instead of being hoisted out of the step loop (which turns
+// them into spills).  The radix-16 engine keeps them in registers.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+    __asm__ volatile("" : "+s"(p));
+    return p;
+}
+template <int NN>
+__device__ __forceinline__ void reload_pot(const GpeArgs& A, double (&v0)[Lay<NN>::P],
+                                           double (&v1)[Lay<NN>::P]) {
+    if constexpr (Lay<NN>::P == 8) {
+        constexpr int T = Lay<NN>::T;
+        const double* V0 = opaque(A.V0) + threadIdx.x;
+        const double* V1 = opaque(A.V1) + threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            v0[i] = V0[T * i];
+            v1[i] = V1[T * i];
+        }
+    }
+}
+
 // Forward steps j0 .. j1-1 from x = a_{j0}, storing a_j in traj_b.  After the last step:
 // psi_{j1} = F^-1 Kh F b_{j1-1} is formed (and written to psi_out if given) when psi_out or
 // cont is set, and with cont x = a_{j1} = F^-1 Kh F psi_{j1} on return.
 template <int NN, typename R>
-__device__ void fwd_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, Cd (&x)[16],
-                        const double (&v0)[16], const double (&v1)[16], Cx<R>* traj_b,
-                        dcx* psi_out, bool cont) {
-    constexpr int T = NN / 16;
+__device__ void fwd_run(const GpeArgs& A, const Lds& L, const Eng<NN>& E, int b, int j0,
+                        int j1, Cd (&x)[Lay<NN>::P], double (&v0)[Lay<NN>::P],
+                        double (&v1)[Lay<NN>::P], Cx<R>* traj_b, dcx* psi_out, bool cont) {
+    constexpr int T = Lay<NN>::T, P = Lay<NN>::P;
     const int t = threadIdx.x;
+    const auto reload = [&] { reload_pot<NN>(A, v0, v1); };
     const double* ub = A.u + (size_t)b * A.K;
     double un = ub[j0];
     for (int j = j0; j < j1; ++j) {
         Cx<R>* tj = traj_b + (size_t)j * NN;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) tj[t + T * i] = down<R>(x[i]);
+        for (int i = 0; i < P; ++i) tj[t + T * i] = down<R>(x[i]);
         const bool last = j == j1 - 1;
         if (last && !psi_out && !cont) return;
         const double u = un;
         if (!last) un = ub[j + 1];                        // next step's control, ahead of use
 #pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, x[i]));
+        for (int i = 0; i < P; ++i) x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, x[i]));
         if (!last) {
-            kick<NN, false>(x, L, nullptr);
+            kick<NN, false>(x, L, E, nullptr, reload);
         } else {
-            kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
+            kick<NN, false>(x, L, E, reinterpret_cast<const Cd*>(A.Kh), reload);
             if (psi_out) store_state<NN>(psi_out, x);
-            if (cont) kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
+            if (cont) kick<NN, false>(x, L, E, reinterpret_cast<const Cd*>(A.Kh), reload);
         }
     }
 }
@@ -395,38 +625,52 @@ __device__ void fwd_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
 // writes it, and continues to x = nu'_{j0-1}.  With grad_on every step's gradient is formed
 // and, with upd, the update u_j += rho g_j applied (u_j is not read again here).
 template <int NN, typename R>
-__device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, Cd (&x)[16],
-                        const double (&v0)[16], const double (&v1)[16], const Cx<R>* traj_b,
-                        dcx* nu_out, int final_kick, bool grad_on, bool upd) {
-    constexpr int T = NN / 16;
+__device__ void adj_run(const GpeArgs& A, const Lds& L, const Eng<NN>& E, int b, int j0,
+                        int j1, Cd (&x)[Lay<NN>::P], double (&v0)[Lay<NN>::P],
+                        double (&v1)[Lay<NN>::P], const Cx<R>* traj_b, dcx* nu_out,
+                        int final_kick, bool grad_on, bool upd) {
+    constexpr int T = Lay<NN>::T, P = Lay<NN>::P;
     const int t = threadIdx.x;
     const Cd* conjKh = reinterpret_cast<const Cd*>(A.Kh);
     double* ub = A.u + (size_t)b * A.K;
     // u_j of the next step down is requested one step ahead (u_{j-1} is read before this
-    // loop updates it); so is a_j in the FP32 path, whose copy costs half the registers
-    constexpr bool kAhead = sizeof(R) == 4;
-    Cx<R> an[16];
+    // loop updates it); so is a_j in the FP32 path, whose copy costs half the registers,
+    // and in both paths of the radix-8 engine, whose kick requests it in its last pass
+    constexpr bool kHook = P == 8;
+    constexpr bool kAhead = kHook || sizeof(R) == 4;
+    Cx<R> an[P];
+    int jn = j1 - 1;                  // row requested by the next kick's hook
+    const auto reload = [&] { reload_pot<NN>(A, v0, v1); };
+    const auto reload_ahead = [&] {
+        reload_pot<NN>(A, v0, v1);
+        if constexpr (kHook) {
+            const Cx<R>* row = opaque(traj_b) + (size_t)jn * NN + t;
+#pragma unroll
+            for (int i = 0; i < P; ++i) an[i] = row[T * i];
+        }
+    };
     double un = ub[j1 - 1];
     if (kAhead) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) an[i] = traj_b[(size_t)(j1 - 1) * NN + t + T * i];
+        for (int i = 0; i < P; ++i) an[i] = traj_b[(size_t)(j1 - 1) * NN + t + T * i];
     }
     for (int j = j1 - 1; j >= j0; --j) {
         const double u = un;
-        Cd av[16];
+        Cd av[P];
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < P; ++i)
             av[i] = up<R>(kAhead ? an[i] : traj_b[(size_t)j * NN + t + T * i]);
         if (j > j0) {
             un = ub[j - 1];
-            if (kAhead) {
+            jn = j - 1;
+            if (kAhead && !kHook) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) an[i] = traj_b[(size_t)(j - 1) * NN + t + T * i];
+                for (int i = 0; i < P; ++i) an[i] = traj_b[(size_t)(j - 1) * NN + t + T * i];
             }
         }
         double part = 0.0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < P; ++i) {
             const Cd a = av[i];
             const Cd e = phase<R>(A, v0[i], v1[i], u, a);
             if (grad_on) {
@@ -448,11 +692,11 @@ __device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
             }
         }
         if (j > j0) {
-            kick<NN, true>(x, L, nullptr);
+            kick<NN, true>(x, L, E, nullptr, reload_ahead);
         } else if (final_kick > 0) {
-            kick<NN, true>(x, L, conjKh);
+            kick<NN, true>(x, L, E, conjKh, reload);
             if (nu_out) store_state<NN>(nu_out, x);
-            if (final_kick == 2) kick<NN, true>(x, L, conjKh);
+            if (final_kick == 2) kick<NN, true>(x, L, E, conjKh, reload);
         }
     }
 }
@@ -460,26 +704,28 @@ __device__ void adj_run(const GpeArgs& A, const Lds& L, int b, int j0, int j1, C
 // Sequential forward sweep of one instance: psi(t_n) for every n, a_j for every step,
 // J and F at T.
 template <int NN, typename R>
-__global__ __launch_bounds__(NN / 16) void k_gpe_fwd_sweep(GpeArgs A) {
+__global__ __launch_bounds__(Lay<NN>::T) void k_gpe_fwd_sweep(GpeArgs A) {
     extern __shared__ unsigned char smem_raw[];
     const Lds L = lds_carve<NN>(smem_raw);
     const int b = blockIdx.x;
-    double v0[16], v1[16];
-    setup<NN>(A, L, v0, v1);
+    constexpr int P = Lay<NN>::P;
+    double v0[P], v1[P];
+    Eng<NN> E;
+    setup<NN>(A, L, E, v0, v1);
     dcx* Psi_b = A.Psi + (size_t)b * (A.N + 1) * NN;
     Cx<R>* traj_b = reinterpret_cast<Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
-    Cd x[16];
+    Cd x[P];
     load_state<NN>(x, A.psi0);
     store_state<NN>(Psi_b, x);
-    kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));      // a_0
+    kick<NN, false>(x, L, E, reinterpret_cast<const Cd*>(A.Kh));      // a_0
     for (int nn = 0; nn < A.N; ++nn)
-        fwd_run<NN, R>(A, L, b, A.s[nn], A.s[nn + 1], x, v0, v1, traj_b,
+        fwd_run<NN, R>(A, L, E, b, A.s[nn], A.s[nn + 1], x, v0, v1, traj_b,
                        Psi_b + (size_t)(nn + 1) * NN, nn + 1 < A.N);
     // x = psi_K:  J = Re <psi_K|psi_f> dx,  F = |<psi_K|psi_f> dx|^2
-    constexpr int T = NN / 16;
+    constexpr int T = Lay<NN>::T;
     double zr = 0.0, zi = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < P; ++i) {
         const dcx f = A.target[threadIdx.x + T * i];
         zr += x[i].re * f.re + x[i].im * f.im;
         zi += x[i].re * f.im - x[i].im * f.re;
@@ -501,43 +747,47 @@ __global__ __launch_bounds__(NN / 16) void k_gpe_fwd_sweep(GpeArgs A) {
 
 // Sequential adjoint sweep of one instance: nu(t_n) for every n.
 template <int NN, typename R>
-__global__ __launch_bounds__(NN / 16) void k_gpe_adj_sweep(GpeArgs A) {
+__global__ __launch_bounds__(Lay<NN>::T) void k_gpe_adj_sweep(GpeArgs A) {
     extern __shared__ unsigned char smem_raw[];
     const Lds L = lds_carve<NN>(smem_raw);
     const int b = blockIdx.x;
-    double v0[16], v1[16];
-    setup<NN>(A, L, v0, v1);
+    constexpr int P = Lay<NN>::P;
+    double v0[P], v1[P];
+    Eng<NN> E;
+    setup<NN>(A, L, E, v0, v1);
     dcx* Lam_b = A.Lam + (size_t)b * (A.N + 1) * NN;
     const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
-    Cd x[16];
+    Cd x[P];
     load_state<NN>(x, A.target);
     store_state<NN>(Lam_b + (size_t)A.N * NN, x);
-    kick<NN, true>(x, L, reinterpret_cast<const Cd*>(A.Kh));       // nu'_{K-1}
+    kick<NN, true>(x, L, E, reinterpret_cast<const Cd*>(A.Kh));       // nu'_{K-1}
     for (int nn = A.N - 1; nn >= 0; --nn)
-        adj_run<NN, R>(A, L, b, A.s[nn], A.s[nn + 1], x, v0, v1, traj_b,
+        adj_run<NN, R>(A, L, E, b, A.s[nn], A.s[nn + 1], x, v0, v1, traj_b,
                        Lam_b + (size_t)nn * NN, nn > 0 ? 2 : 1, false, false);
 }
 
 // Slice n of instance b: forward from psi(t_n), adjoint from nu(t_{n+1}), gradient, update.
 template <int NN, typename R>
-__global__ __launch_bounds__(NN / 16) void k_gpe_slice(GpeArgs A) {
+__global__ __launch_bounds__(Lay<NN>::T) void k_gpe_slice(GpeArgs A) {
     extern __shared__ unsigned char smem_raw[];
     const Lds L = lds_carve<NN>(smem_raw);
     const int nn = blockIdx.x, b = blockIdx.y;
-    double v0[16], v1[16];
-    setup<NN>(A, L, v0, v1);
+    constexpr int P = Lay<NN>::P;
+    double v0[P], v1[P];
+    Eng<NN> E;
+    setup<NN>(A, L, E, v0, v1);
     const int j0 = A.s[nn], j1 = A.s[nn + 1];
     Cx<R>* traj_b = reinterpret_cast<Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
     const dcx* Psi_b = A.Psi + (size_t)b * (A.N + 1) * NN;
     const dcx* Lam_b = A.Lam + (size_t)b * (A.N + 1) * NN;
-    Cd x[16];
+    Cd x[P];
     load_state<NN>(x, Psi_b + (size_t)nn * NN);
-    kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));      // a_{j0}
-    fwd_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b, nullptr, false);
+    kick<NN, false>(x, L, E, reinterpret_cast<const Cd*>(A.Kh));      // a_{j0}
+    fwd_run<NN, R>(A, L, E, b, j0, j1, x, v0, v1, traj_b, nullptr, false);
     load_state<NN>(x, Lam_b + (size_t)(nn + 1) * NN);
-    kick<NN, true>(x, L, reinterpret_cast<const Cd*>(A.Kh));       // nu'_{j1-1}
+    kick<NN, true>(x, L, E, reinterpret_cast<const Cd*>(A.Kh));       // nu'_{j1-1}
     const bool upd = A.update && (A.active == nullptr || A.active[b] != 0);
-    adj_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b, nullptr, 0, true, upd);
+    adj_run<NN, R>(A, L, E, b, j0, j1, x, v0, v1, traj_b, nullptr, 0, true, upd);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -553,54 +803,56 @@ __global__ __launch_bounds__(NN / 16) void k_gpe_slice(GpeArgs A) {
 
 // column v of M_n: S_{j1-1} ... S_{j0} e_v (kinetic half steps fused inside the slice)
 template <int NN, typename R>
-__global__ __launch_bounds__(NN / 16) void k_gpe_frozen_fwd(GpeArgs A, dcx* M) {
+__global__ __launch_bounds__(Lay<NN>::T) void k_gpe_frozen_fwd(GpeArgs A, dcx* M) {
     extern __shared__ unsigned char smem_raw[];
     const Lds L = lds_carve<NN>(smem_raw);
     const int v = blockIdx.x, nn = blockIdx.y, b = blockIdx.z;
-    constexpr int T = NN / 16;
+    constexpr int T = Lay<NN>::T, P = Lay<NN>::P;
     const int t = threadIdx.x;
-    double v0[16], v1[16];
-    setup<NN>(A, L, v0, v1);
+    double v0[P], v1[P];
+    Eng<NN> E;
+    setup<NN>(A, L, E, v0, v1);
     const int j0 = A.s[nn], j1 = A.s[nn + 1];
     const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
     const double* ub = A.u + (size_t)b * A.K;
-    Cd x[16];
+    Cd x[P];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = Cd{t + T * i == v ? 1.0 : 0.0, 0.0};
-    kick<NN, false>(x, L, reinterpret_cast<const Cd*>(A.Kh));
+    for (int i = 0; i < P; ++i) x[i] = Cd{t + T * i == v ? 1.0 : 0.0, 0.0};
+    kick<NN, false>(x, L, E, reinterpret_cast<const Cd*>(A.Kh));
     for (int j = j0; j < j1; ++j) {
         const double u = ub[j];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < P; ++i) {
             const Cd af = up<R>(traj_b[(size_t)j * NN + t + T * i]);     // frozen a_j
             x[i] = cmul(x[i], phase<R>(A, v0[i], v1[i], u, af));
         }
-        kick<NN, false>(x, L, j + 1 < j1 ? nullptr : reinterpret_cast<const Cd*>(A.Kh));
+        kick<NN, false>(x, L, E, j + 1 < j1 ? nullptr : reinterpret_cast<const Cd*>(A.Kh));
     }
     store_state<NN>(M + (((size_t)b * A.N + nn) * NN + v) * NN, x);
 }
 
 // column c of A_n: R_{j0} ... R_{j1-1} applied to e_c (c < n) or i e_{c-n}
 template <int NN, typename R>
-__global__ __launch_bounds__(NN / 16) void k_gpe_frozen_adj(GpeArgs A, dcx* Aj) {
+__global__ __launch_bounds__(Lay<NN>::T) void k_gpe_frozen_adj(GpeArgs A, dcx* Aj) {
     extern __shared__ unsigned char smem_raw[];
     const Lds L = lds_carve<NN>(smem_raw);
     const int c = blockIdx.x, nn = blockIdx.y, b = blockIdx.z;
-    constexpr int T = NN / 16;
+    constexpr int T = Lay<NN>::T, P = Lay<NN>::P;
     const int t = threadIdx.x;
-    double v0[16], v1[16];
-    setup<NN>(A, L, v0, v1);
+    double v0[P], v1[P];
+    Eng<NN> E;
+    setup<NN>(A, L, E, v0, v1);
     const int j0 = A.s[nn], j1 = A.s[nn + 1];
     const Cx<R>* traj_b = reinterpret_cast<const Cx<R>*>(A.traj) + (size_t)b * A.K * NN;
     const int m = c < NN ? c : c - NN;
-    Cd x[16];
+    Cd x[P];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < P; ++i) {
         const bool on = t + T * i == m;
         x[i] = c < NN ? Cd{on ? 1.0 : 0.0, 0.0} : Cd{0.0, on ? 1.0 : 0.0};
     }
-    kick<NN, true>(x, L, reinterpret_cast<const Cd*>(A.Kh));
-    adj_run<NN, R>(A, L, b, j0, j1, x, v0, v1, traj_b,
+    kick<NN, true>(x, L, E, reinterpret_cast<const Cd*>(A.Kh));
+    adj_run<NN, R>(A, L, E, b, j0, j1, x, v0, v1, traj_b,
                    Aj + (((size_t)b * A.N + nn) * 2 * NN + c) * NN, 1, false, false);
 }
 
@@ -703,7 +955,8 @@ static void gpe_free(ism_problem* p) {
 
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision) {
     const size_t rs = precision == ISM_FP64 ? 16 : 8;
-    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 2 + 768) * 16;
+    const size_t ntab = n == 4096 ? 4096 : 768;
+    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 2 + ntab) * 16;
 }
 
 size_t gpe_frozen_bytes(size_t n, int N, int batch) {
@@ -740,17 +993,19 @@ static GpeArgs gpe_args(ism_problem* p) {
     return A;
 }
 
-// exchange buffer (padded), kinetic factors, twiddle tables, reduction slots; FP64 in both
-// precisions
+// FP64 in both precisions.  n = 4096: two exchange buffers and the reduction slots (the
+// engine's constants are in registers); otherwise the padded exchange buffer, kinetic
+// factors, twiddle tables and reduction slots
 static size_t gpe_shmem(int n) {
+    if (n == 4096) return (4 * ((size_t)n + n / 8) + 2 * 504 + 16) * sizeof(double);
     return ((size_t)n + n / 16 + (size_t)n / 2 + 1 + 768) * sizeof(dcx) +
            2 * ((size_t)n / 2 + 1) * sizeof(double) + 16 * sizeof(double);
 }
 
 template <int NN, typename R>
 static void gpe_launch_sweeps_n(const GpeArgs& A, hipStream_t st, size_t shm) {
-    hipLaunchKernelGGL((k_gpe_fwd_sweep<NN, R>), dim3(A.B), dim3(NN / 16), shm, st, A);
-    hipLaunchKernelGGL((k_gpe_adj_sweep<NN, R>), dim3(A.B), dim3(NN / 16), shm, st, A);
+    hipLaunchKernelGGL((k_gpe_fwd_sweep<NN, R>), dim3(A.B), dim3(Lay<NN>::T), shm, st, A);
+    hipLaunchKernelGGL((k_gpe_adj_sweep<NN, R>), dim3(A.B), dim3(Lay<NN>::T), shm, st, A);
 }
 
 template <typename R>
@@ -763,11 +1018,11 @@ static void gpe_launch_sweeps(const GpeArgs& A, hipStream_t st, size_t shm) {
 template <typename R>
 static void gpe_launch_slice(const GpeArgs& A, hipStream_t st, size_t shm) {
     if (A.n == 4096)
-        hipLaunchKernelGGL((k_gpe_slice<4096, R>), dim3(A.N, A.B), dim3(256), shm, st, A);
+        hipLaunchKernelGGL((k_gpe_slice<4096, R>), dim3(A.N, A.B), dim3(Lay<4096>::T), shm, st, A);
     else if (A.n == 1024)
-        hipLaunchKernelGGL((k_gpe_slice<1024, R>), dim3(A.N, A.B), dim3(64), shm, st, A);
+        hipLaunchKernelGGL((k_gpe_slice<1024, R>), dim3(A.N, A.B), dim3(Lay<1024>::T), shm, st, A);
     else
-        hipLaunchKernelGGL((k_gpe_slice<64, R>), dim3(A.N, A.B), dim3(4), shm, st, A);
+        hipLaunchKernelGGL((k_gpe_slice<64, R>), dim3(A.N, A.B), dim3(Lay<64>::T), shm, st, A);
 }
 
 template <int NN, typename R>
@@ -788,9 +1043,9 @@ static void gpe_launch_frozen(ism_problem* p, const GpeArgs& A, GpeExt* x, size_
     const int B = A.B, N = A.N;
     {
         TimeScope ts(p, KID_GPE_ASSEMBLE);
-        hipLaunchKernelGGL((k_gpe_frozen_fwd<NN, R>), dim3(NN, N, B), dim3(NN / 16), shm,
+        hipLaunchKernelGGL((k_gpe_frozen_fwd<NN, R>), dim3(NN, N, B), dim3(Lay<NN>::T), shm,
                            p->stream, A, x->fM);
-        hipLaunchKernelGGL((k_gpe_frozen_adj<NN, R>), dim3(2 * NN, N, B), dim3(NN / 16), shm,
+        hipLaunchKernelGGL((k_gpe_frozen_adj<NN, R>), dim3(2 * NN, N, B), dim3(Lay<NN>::T), shm,
                            p->stream, A, x->fA);
     }
     TimeScope ts(p, KID_GPE_BOUNDARY);
@@ -902,13 +1157,17 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
         const long double a = 2.0L * PIL * (long double)e / (long double)m;
         return dcx{(double)cosl(a), (double)-sinl(a)};
     };
-    std::vector<dcx> tab(768), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
-    for (int r = 0; r < 16; ++r)
-        for (int k = 0; k < 16; ++k) {
-            tab[r * 16 + k] = root((long long)r * k, 256);              // pass 2
-            tab[256 + r * 16 + k] = root(16LL * r * k, n);              // pass 3, high part
-            tab[512 + r * 16 + k] = root((long long)r * k, n);          // pass 3, low part
-        }
+    std::vector<dcx> tab(n == 4096 ? 4096 : 768), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
+    if (n == 4096) {                          // radix-8 engine: every root W_4096^m
+        for (int m = 0; m < 4096; ++m) tab[m] = root(m, 4096);
+    } else {
+        for (int r = 0; r < 16; ++r)
+            for (int k = 0; k < 16; ++k) {
+                tab[r * 16 + k] = root((long long)r * k, 256);          // pass 2
+                tab[256 + r * 16 + k] = root(16LL * r * k, n);          // pass 3, high part
+                tab[512 + r * 16 + k] = root((long long)r * k, n);      // pass 3, low part
+            }
+    }
     // wavenumbers k_f = 2 pi f / (n dx) in FP64, formed as (2 pi) (f (1 / (n dx))) with
     // dx = L / n (the grid's frequencies in the usual fftfreq order); the kinetic phase
     // -tau k^2 / 4 and its exponential are then evaluated in extended precision

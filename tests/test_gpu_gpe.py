@@ -53,6 +53,9 @@ CASES = [
     ("n1024_K41_N4", lambda: _small()),
     ("n1024_K12_N12", lambda: _small(K=12, N=12)),
     ("n4096_K30_N1", lambda: _small(n=4096, K=30, N=1)),
+    ("n4096_K37_N5_batch2", lambda: _small(n=4096, K=37, N=5, batch=2)),
+    ("n4096_K9_N9", lambda: _small(n=4096, K=9, N=9)),
+    ("n4096_K1_N1_single_step", lambda: _small(n=4096, K=1, N=1, T=0.01)),
     ("n1024_g0_K25_N5", lambda: _small(K=25, N=5, g=0.0)),
     ("n1024_batch2", lambda: _small(K=20, N=3, batch=2)),
     ("n1024_K1_N1_single_step", lambda: _small(K=1, N=1, T=0.01)),
@@ -102,6 +105,20 @@ def test_gpe_iterate_equals_plain():
         Jh, done = h.iterate(4, 0.1)
         u = h.get_controls()[0, :, 0]
     assert done == 4
+    assert np.max(np.abs(Jh[:, 0] - ref["J"])) <= 1e-12
+    assert np.max(np.abs(u - ref["u"])) <= 1e-12
+
+
+def test_gpe_iterate_equals_plain_n4096():
+    _say("case gpe iterate n4096")
+    P = _P()
+    p = _small(n=4096, K=26, N=4)
+    ref = G.plain_gradient_method(p.psi0, p.target, p.u0[0, :, 0], p.V0, p.V1, p.V2, p.g, p.L,
+                                  p.T, 0.1, 3)
+    with P.from_problem(p, precision="fp64") as h:
+        Jh, done = h.iterate(3, 0.1)
+        u = h.get_controls()[0, :, 0]
+    assert done == 3
     assert np.max(np.abs(Jh[:, 0] - ref["J"])) <= 1e-12
     assert np.max(np.abs(u - ref["u"])) <= 1e-12
 
