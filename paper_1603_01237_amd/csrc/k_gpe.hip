@@ -27,13 +27,15 @@
 // trajectory and the gradient terms are formed in registers and only the exchanges between
 // passes go through LDS (split real and imaginary planes of 8-byte words).
 //  * n = 4096: P = 8, 512 threads (two wavefronts per SIMD), radices 8, 8, 8, 8.  The
-//    per-lane twiddles of the three twiddled passes and the kinetic factors at the owned
-//    frequencies stay in registers for the whole launch; the three exchanges of a transform
-//    alternate between two LDS buffers, so each needs one barrier (a buffer is written
-//    again only after the barrier that follows its last reads), and an XOR swizzle of the
-//    word index makes every access pattern bank-conflict free.
-//  * n = 1024 and 64: P = 16, radices 16, 16, 4 and 16, 4, with one in-place buffer padded
-//    by one element per 16 and the kinetic factors and twiddles in LDS tables.
+//    pass-3 twiddles and the kinetic factors at the owned frequencies stay in registers for
+//    the whole launch, the pass-1/2 twiddles in an LDS table; the three exchanges of a
+//    transform alternate between two LDS buffers of 16-byte complex slots, so each needs
+//    one barrier (a buffer is written again only after the barrier that follows its last
+//    reads), and each exchange has its own padding, which makes all its accesses
+//    bank-conflict free and each a per-thread base plus a compile-time offset.
+//  * n = 1024 and 64: P = 16, radices 16, 16, 4 and 16, 4, with one in-place buffer of split
+//    real and imaginary planes padded by one element per 16 and the kinetic factors and
+//    twiddles in LDS tables.
 // Butterflies, twiddles and the LDS state are FP64 in both precisions; the FP32 mixed path
 // stores the trajectory a_j and forms the phase e^{-i theta} in FP32.
 #include <math.h>
@@ -49,6 +51,8 @@ namespace {
 
 template <typename R> struct Cx { R re, im; };
 using Cd = Cx<double>;
+
+constexpr int kSlots8 = 4608;     // slots of an exchange buffer of the radix-8 engine
 
 // points per thread and threads per workgroup of the FFT engine for grid size NN
 template <int NN> struct Lay {
@@ -160,25 +164,30 @@ __device__ __forceinline__ void dft8(Cd (&x)[8]) {
     x[7] = Cd{e3.re - o3.re, e3.im - o3.im};
 }
 
-// word of element i in a plane of the radix-8 exchange buffers: one word of padding per 8.
-// Every access of an exchange is then a per-thread base plus a compile-time offset (writes
-// 8t + c -> 9t + c; 64 (t >> 3) + 8c + (t & 7) -> 72 (t >> 3) + (t & 7) + 9c;
-// 512 (t >> 6) + 64c + (t & 63) -> pad(512 (t >> 6) + (t & 63)) + 72c; reads t + 512 r ->
-// pad(t) + 576 r), so no address register is held per access; within 16 consecutive lanes
-// the writes of passes 0 and 1 fall on distinct 8-byte bank pairs, and the reads and the
-// writes of pass 2 on 15 distinct pairs (one pair shared by two lanes).
-__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+// 16-byte complex slot of the radix-8 exchanges (one ds_read_b128 / ds_write_b128 each)
+struct alignas(16) Cl {
+    double re, im;
+};
+
+// Slot of element i in the three exchanges of a transform (A after pass 0, B after pass 1,
+// C after pass 2): A: i + (i >> 4), B: i + 2 (i >> 4), C: i.  Every access is then a
+// per-thread base plus a compile-time offset, and the 16 lanes served together by the LDS
+// hit 16 distinct slots modulo 16 (distinct banks) in every pattern:
+//   A: writes 8t + c at 8t + (t >> 1) + c;  reads t + 512 r at t + (t >> 4) + 544 r
+//   B: writes 64 (t >> 3) + 8c + (t & 7) at 72 (t >> 3) + (t & 7) + 8c + 2 (c >> 1);
+//      reads at t + 2 (t >> 4) + 576 r
+//   C: writes 512 (t >> 6) + 64c + (t & 63) at the same slot; reads at t + 512 r
 
 // LDS carve-up of a workgroup.  Complex arrays are split into real and imaginary planes of
 // doubles: the exchange accesses are then 8-byte words on consecutive (padded) addresses,
 // which the LDS serves without bank conflicts (interleaved pairs put lanes 16 bytes apart).
 struct Lds {
     double* sr;        // P = 16: n + n/16, padded FFT exchange buffer, real plane;
-    double* si;        //         imaginary plane.  P = 8: exchange buffer 0 (n each)
-    double* sr1;       // P = 8: exchange buffer 1
-    double* si1;
-    double* wr;        // P = 8: twiddles of passes 1 and 2, [r-1][k]: W_64^{r k} at
-    double* wi;        //        (r-1) 8 + k (k < 8), then W_512^{r k} at 56 + (r-1) 64 + k
+    double* si;        //         imaginary plane
+    Cl* x0;            // P = 8: exchange buffers (4608 slots each)
+    Cl* x1;
+    Cl* tw;            // P = 8: twiddles of passes 1 and 2, [r-1][k]: W_64^{r k} at
+                       //        (r-1) 8 + k (k < 8), then W_512^{r k} at 56 + (r-1) 64 + k
     double* kr;        // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| = 0..n/2, rounded
     double* ki;
     double* klr;       // n/2 + 1: its rounding residual (exact factor = kr + klr)
@@ -200,14 +209,10 @@ template <int NN>
 __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
     Lds L{};
     if constexpr (Lay<NN>::P == 8) {
-        constexpr int PN = NN + NN / 8;
-        L.sr = reinterpret_cast<double*>(raw);
-        L.si = L.sr + PN;
-        L.sr1 = L.si + PN;
-        L.si1 = L.sr1 + PN;
-        L.wr = L.si1 + PN;
-        L.wi = L.wr + 504;
-        L.red = L.wi + 504;
+        L.x0 = reinterpret_cast<Cl*>(raw);
+        L.x1 = L.x0 + kSlots8;
+        L.tw = L.x1 + kSlots8;
+        L.red = reinterpret_cast<double*>(L.tw + 504);
         return L;
     }
     constexpr int PN = NN + NN / 16;
@@ -238,44 +243,38 @@ struct Eng16 {};
 template <int NN>
 using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8, Eng16>;
 
-// one exchange of the radix-8 engine: element i of the plane pair (re, im)
-__device__ __forceinline__ void st8(double* re, double* im, int i, Cd v) {
-    re[pad8(i)] = v.re;
-    im[pad8(i)] = v.im;
-}
-__device__ __forceinline__ Cd ld8(const double* re, const double* im, int i) {
-    return Cd{re[pad8(i)], im[pad8(i)]};
-}
-
 // Radix-8 Stockham pass p = 1, 2, 3 over sub-transforms of size S = 8^p: thread t reads
-// x_r = A[t + 512 r], multiplies by W_{8S}^{r (t mod S)} and forms the 8-point DFT; passes 1
-// and 2 write y_c to B[8S (t / S) + S c + (t mod S)], pass 3 keeps X[t + 512 c] = y_c.
+// x_r = A[t + 512 r] (exchange A, B or C), multiplies by W_{8S}^{r (t mod S)} and forms the
+// 8-point DFT; passes 1 and 2 write y_c to B[8S (t / S) + S c + (t mod S)] (exchange B or C),
+// pass 3 keeps X[t + 512 c] = y_c.
 template <int SIGN, int PASS>
-__device__ __forceinline__ void pass8(Cd (&x)[8], const double* ar, const double* ai,
-                                      double* br, double* bi, const Lds& L, const Eng8& E) {
+__device__ __forceinline__ void pass8(Cd (&x)[8], const Cl* a, Cl* b, const Lds& L,
+                                      const Eng8& E) {
     const int t = threadIdx.x;
-    const double* pr = ar + pad8(t);
-    const double* pi = ai + pad8(t);
+    const Cl* pa = a + (PASS == 1 ? t + (t >> 4) : PASS == 2 ? t + 2 * (t >> 4) : t);
+    constexpr int RS = PASS == 1 ? 544 : PASS == 2 ? 576 : 512;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) x[r] = Cd{pr[576 * r], pi[576 * r]};
+    for (int r = 0; r < 8; ++r) {
+        const Cl v = pa[RS * r];
+        x[r] = Cd{v.re, v.im};
+    }
 #pragma unroll
     for (int r = 1; r < 8; ++r) {
-        Cd w;
-        if constexpr (PASS == 1) w = Cd{L.wr[(r - 1) * 8 + (t & 7)], L.wi[(r - 1) * 8 + (t & 7)]};
-        else if constexpr (PASS == 2)
-            w = Cd{L.wr[56 + (r - 1) * 64 + (t & 63)], L.wi[56 + (r - 1) * 64 + (t & 63)]};
-        else w = E.tw[r - 1];
-        x[r] = cmul_s<SIGN>(x[r], w);
+        Cl w;
+        if constexpr (PASS == 1) w = L.tw[(r - 1) * 8 + (t & 7)];
+        else if constexpr (PASS == 2) w = L.tw[56 + (r - 1) * 64 + (t & 63)];
+        else w = Cl{E.tw[r - 1].re, E.tw[r - 1].im};
+        x[r] = cmul_s<SIGN>(x[r], Cd{w.re, w.im});
     }
     dft8<SIGN>(x);
-    if constexpr (PASS < 3) {
-        constexpr int S = PASS == 1 ? 8 : 64;
-        const int base = pad8((t / S) * 8 * S + (t & (S - 1)));
+    if constexpr (PASS == 1) {
+        Cl* pb = b + 72 * (t >> 3) + (t & 7);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {        // pad8(base + S c) = pad8(base) + (9 S / 8) c
-            br[base + (9 * S / 8) * c] = x[c].re;
-            bi[base + (9 * S / 8) * c] = x[c].im;
-        }
+        for (int c = 0; c < 8; ++c) pb[8 * c + 2 * (c >> 1)] = Cl{x[c].re, x[c].im};
+    } else if constexpr (PASS == 2) {
+        Cl* pb = b + 512 * (t >> 6) + (t & 63);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) pb[64 * c] = Cl{x[c].re, x[c].im};
     }
 }
 
@@ -285,24 +284,20 @@ __device__ __forceinline__ void pass8(Cd (&x)[8], const double* ar, const double
 // loads issued there have that pass to arrive in.
 template <int SIGN, typename Hook>
 __device__ __forceinline__ void fft8e(Cd (&x)[8], const Lds& L, const Eng8& E, Hook&& hook) {
-    double* ar = SIGN < 0 ? L.sr : L.sr1;
-    double* ai = SIGN < 0 ? L.si : L.si1;
-    double* br = SIGN < 0 ? L.sr1 : L.sr;
-    double* bi = SIGN < 0 ? L.si1 : L.si;
+    Cl* u = SIGN < 0 ? L.x0 : L.x1;
+    Cl* v = SIGN < 0 ? L.x1 : L.x0;
     const int t = threadIdx.x;
     dft8<SIGN>(x);                               // pass 0: sub-transform size 1
+    Cl* pu = u + 8 * t + (t >> 1);               // exchange A
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {                // pad8(8t + c) = 9t + c
-        ar[9 * t + c] = x[c].re;
-        ai[9 * t + c] = x[c].im;
-    }
+    for (int c = 0; c < 8; ++c) pu[c] = Cl{x[c].re, x[c].im};
     lds_sync();
-    pass8<SIGN, 1>(x, ar, ai, br, bi, L, E);
+    pass8<SIGN, 1>(x, u, v, L, E);               // A -> B
     lds_sync();
-    pass8<SIGN, 2>(x, br, bi, ar, ai, L, E);
+    pass8<SIGN, 2>(x, v, u, L, E);               // B -> C
     lds_sync();
     hook();
-    pass8<SIGN, 3>(x, ar, ai, nullptr, nullptr, L, E);
+    pass8<SIGN, 3>(x, u, nullptr, L, E);         // C -> registers
 }
 
 // radix-16 engine (n = 1024, 64)
@@ -452,8 +447,7 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E
         // W_64^{r k} = W_4096^{64 r k}, W_512^{r k} = W_4096^{8 r k}
         for (int i = t; i < 504; i += T) {
             const int m = i < 56 ? 64 * (i / 8 + 1) * (i & 7) : 8 * ((i - 56) / 64 + 1) * ((i - 56) & 63);
-            L.wr[i] = A.tab[m].re;
-            L.wi[i] = A.tab[m].im;
+            L.tw[i] = Cl{A.tab[m].re, A.tab[m].im};
         }
 #pragma unroll
         for (int r = 1; r < 8; ++r) {
@@ -997,7 +991,7 @@ static GpeArgs gpe_args(ism_problem* p) {
 // engine's constants are in registers); otherwise the padded exchange buffer, kinetic
 // factors, twiddle tables and reduction slots
 static size_t gpe_shmem(int n) {
-    if (n == 4096) return (4 * ((size_t)n + n / 8) + 2 * 504 + 16) * sizeof(double);
+    if (n == 4096) return (2 * (size_t)kSlots8 + 504) * 16 + 16 * sizeof(double);
     return ((size_t)n + n / 16 + (size_t)n / 2 + 1 + 768) * sizeof(dcx) +
            2 * ((size_t)n / 2 + 1) * sizeof(double) + 16 * sizeof(double);
 }
