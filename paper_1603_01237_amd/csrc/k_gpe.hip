@@ -229,12 +229,16 @@ __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
     return L;
 }
 
-// Per-lane constants of the radix-8 engine (n = 4096, thread t), loaded once per launch:
-//   tw[r-1] = W_4096^{r t}, the twiddles of pass 3 (r = 1..7; passes 1 and 2 read theirs
+// Constants of the radix-8 engine (n = 4096, thread t), loaded once per launch:
+//   w1[c-1] = W_64^{w c}, w = t >> 6 the thread's wavefront: the pass-1 twiddle of element
+//   8t + c, which pass 0 applies before its write (pass 1 reads that element as input
+//   r = w of its sub-transform position c); uniform over the wavefront (scalar registers);
+//   tw[r-1] = W_4096^{r t}, the twiddles of pass 3 (r = 1..7; pass 2 reads its twiddles
 //   from an LDS table);
 //   kf[c] + kl[c] = e^{-i tau k^2/2} / n at the owned frequency t + 512 c (rounded value and
 //   its rounding residual, the residual kept in FP32).
 struct Eng8 {
+    Cd w1[7];
     Cd tw[7];
     Cd kf[8];
     Cx<float> kl[8];
@@ -244,8 +248,8 @@ template <int NN>
 using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8, Eng16>;
 
 // Radix-8 Stockham pass p = 1, 2, 3 over sub-transforms of size S = 8^p: thread t reads
-// x_r = A[t + 512 r] (exchange A, B or C), multiplies by W_{8S}^{r (t mod S)} and forms the
-// 8-point DFT; passes 1 and 2 write y_c to B[8S (t / S) + S c + (t mod S)] (exchange B or C),
+// x_r = A[t + 512 r] (exchange A, B or C), multiplies by W_{8S}^{r (t mod S)} (pass 1: done
+// by pass 0 before its write) and forms the 8-point DFT; passes 1 and 2 write y_c to B[8S (t / S) + S c + (t mod S)] (exchange B or C),
 // pass 3 keeps X[t + 512 c] = y_c.
 template <int SIGN, int PASS>
 __device__ __forceinline__ void pass8(Cd (&x)[8], const Cl* a, Cl* b, const Lds& L,
@@ -258,13 +262,14 @@ __device__ __forceinline__ void pass8(Cd (&x)[8], const Cl* a, Cl* b, const Lds&
         const Cl v = pa[RS * r];
         x[r] = Cd{v.re, v.im};
     }
+    if constexpr (PASS != 1) {                  // pass 0 applies the pass-1 twiddles
 #pragma unroll
-    for (int r = 1; r < 8; ++r) {
-        Cl w;
-        if constexpr (PASS == 1) w = L.tw[(r - 1) * 8 + (t & 7)];
-        else if constexpr (PASS == 2) w = L.tw[56 + (r - 1) * 64 + (t & 63)];
-        else w = Cl{E.tw[r - 1].re, E.tw[r - 1].im};
-        x[r] = cmul_s<SIGN>(x[r], Cd{w.re, w.im});
+        for (int r = 1; r < 8; ++r) {
+            Cl w;
+            if constexpr (PASS == 2) w = L.tw[56 + (r - 1) * 64 + (t & 63)];
+            else w = Cl{E.tw[r - 1].re, E.tw[r - 1].im};
+            x[r] = cmul_s<SIGN>(x[r], Cd{w.re, w.im});
+        }
     }
     dft8<SIGN>(x);
     if constexpr (PASS == 1) {
@@ -288,6 +293,8 @@ __device__ __forceinline__ void fft8e(Cd (&x)[8], const Lds& L, const Eng8& E, H
     Cl* v = SIGN < 0 ? L.x1 : L.x0;
     const int t = threadIdx.x;
     dft8<SIGN>(x);                               // pass 0: sub-transform size 1
+#pragma unroll
+    for (int c = 1; c < 8; ++c) x[c] = cmul_s<SIGN>(x[c], E.w1[c - 1]);
     Cl* pu = u + 8 * t + (t >> 1);               // exchange A
 #pragma unroll
     for (int c = 0; c < 8; ++c) pu[c] = Cl{x[c].re, x[c].im};
@@ -449,10 +456,13 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E
             const int m = i < 56 ? 64 * (i / 8 + 1) * (i & 7) : 8 * ((i - 56) / 64 + 1) * ((i - 56) & 63);
             L.tw[i] = Cl{A.tab[m].re, A.tab[m].im};
         }
+        const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
 #pragma unroll
         for (int r = 1; r < 8; ++r) {
             const dcx w = A.tab[(r * t) & (NN - 1)];
             E.tw[r - 1] = Cd{w.re, w.im};
+            const dcx w1 = A.tab[(64 * wv * r) & (NN - 1)];
+            E.w1[r - 1] = Cd{w1.re, w1.im};
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
