@@ -33,9 +33,11 @@
 //    one barrier (a buffer is written again only after the barrier that follows its last
 //    reads), and each exchange has its own padding, which makes all its accesses
 //    bank-conflict free and each a per-thread base plus a compile-time offset.
-//  * n = 1024 and 64: P = 16, radices 16, 16, 4 and 16, 4, with one in-place buffer of split
-//    real and imaginary planes padded by one element per 16 and the kinetic factors and
-//    twiddles in LDS tables.
+//  * n = 64: P = 4, 16 threads (one wavefront), radices 4, 4, 4; twiddles and kinetic factors
+//    in registers, the two exchanges of a transform through two LDS buffers of 16-byte slots.
+//  * n = 1024: P = 16, radices 16, 16, 4, with one in-place buffer of split real and
+//    imaginary planes padded by one element per 16 and the kinetic factors and twiddles in
+//    LDS tables.
 // Butterflies, twiddles and the LDS state are FP64 in both precisions; the FP32 mixed path
 // stores the trajectory a_j and forms the phase e^{-i theta} in FP32.
 #include <math.h>
@@ -56,7 +58,7 @@ constexpr int kSlots8 = 4608;     // slots of an exchange buffer of the radix-8 
 
 // points per thread and threads per workgroup of the FFT engine for grid size NN
 template <int NN> struct Lay {
-    static constexpr int P = NN == 4096 ? 8 : 16;
+    static constexpr int P = NN == 4096 ? 8 : NN == 64 ? 4 : 16;
     static constexpr int T = NN / P;
 };
 
@@ -184,7 +186,7 @@ struct alignas(16) Cl {
 struct Lds {
     double* sr;        // P = 16: n + n/16, padded FFT exchange buffer, real plane;
     double* si;        //         imaginary plane
-    Cl* x0;            // P = 8: exchange buffers (4608 slots each)
+    Cl* x0;            // P = 8: exchange buffers (4608 slots each); P = 4: n slots each
     Cl* x1;
     Cl* tw;            // P = 8: twiddles of passes 1 and 2, [r-1][k]: W_64^{r k} at
                        //        (r-1) 8 + k (k < 8), then W_512^{r k} at 56 + (r-1) 64 + k
@@ -215,6 +217,12 @@ __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
         L.red = reinterpret_cast<double*>(L.tw + 504);
         return L;
     }
+    if constexpr (Lay<NN>::P == 4) {
+        L.x0 = reinterpret_cast<Cl*>(raw);
+        L.x1 = L.x0 + NN;
+        L.red = reinterpret_cast<double*>(L.x1 + NN);
+        return L;
+    }
     constexpr int PN = NN + NN / 16;
     L.sr = reinterpret_cast<double*>(raw);
     L.si = L.sr + PN;
@@ -243,9 +251,18 @@ struct Eng8 {
     Cd kf[8];
     Cx<float> kl[8];
 };
+// Constants of the radix-4 engine (n = 64, thread t < 16): tw[0][r-1] = W_16^{r (t mod 4)},
+// tw[1][r-1] = W_64^{r t} (passes 1 and 2, r = 1..3); kf, kl as for the radix-8 engine at
+// the owned frequencies t + 16 c.
+struct Eng4 {
+    Cd tw[2][3];
+    Cd kf[4];
+    Cx<float> kl[4];
+};
 struct Eng16 {};
 template <int NN>
-using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8, Eng16>;
+using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8,
+                               std::conditional_t<Lay<NN>::P == 4, Eng4, Eng16>>;
 
 // Radix-8 Stockham pass p = 1, 2, 3 over sub-transforms of size S = 8^p: thread t reads
 // x_r = A[t + 512 r] (exchange A, B or C), multiplies by W_{8S}^{r (t mod S)} (pass 1: done
@@ -307,9 +324,41 @@ __device__ __forceinline__ void fft8e(Cd (&x)[8], const Lds& L, const Eng8& E, H
     pass8<SIGN, 3>(x, u, nullptr, L, E);         // C -> registers
 }
 
-// radix-16 engine (n = 1024, 64)
+// radix-4 engine (n = 64, one wavefront of 16 threads): pass p = 0, 1, 2 over sub-transforms
+// of size S = 4^p; thread t reads x_r = A[t + 16 r] (pass 0: its registers), multiplies by
+// W_{4S}^{r (t mod S)} and forms the 4-point DFT; passes 0 and 1 write y_c to
+// B[4S (t / S) + S c + (t mod S)], pass 2 keeps X[t + 16 c] = y_c.  Pass 0 writes buffer 0
+// and pass 1 buffer 1: the next transform's writes come after a barrier that follows every
+// read of the buffer they overwrite.
+template <int SIGN, typename Hook>
+__device__ __forceinline__ void fft4e(Cd (&x)[4], const Lds& L, const Eng4& E, Hook&& hook) {
+    const int t = threadIdx.x;
+    dft4<SIGN>(x[0], x[1], x[2], x[3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) L.x0[4 * t + c] = Cl{x[c].re, x[c].im};
+    lds_sync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const Cl v = L.x0[t + 16 * r];
+        x[r] = r ? cmul_s<SIGN>(Cd{v.re, v.im}, E.tw[0][r - 1]) : Cd{v.re, v.im};
+    }
+    dft4<SIGN>(x[0], x[1], x[2], x[3]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) L.x1[16 * (t >> 2) + 4 * c + (t & 3)] = Cl{x[c].re, x[c].im};
+    lds_sync();
+    hook();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const Cl v = L.x1[t + 16 * r];
+        x[r] = r ? cmul_s<SIGN>(Cd{v.re, v.im}, E.tw[1][r - 1]) : Cd{v.re, v.im};
+    }
+    dft4<SIGN>(x[0], x[1], x[2], x[3]);
+}
+
+// radix-16 engine (n = 1024)
 template <int NN, int SIGN>
 __device__ void fft16e(Cd (&x)[16], const Lds& L) {
+    static_assert(NN == 1024, "radix-16 engine: n = 1024");
     constexpr int T = NN / 16;
     const int t = threadIdx.x;
     // pass 1: radix 16, sub-transform size 1 (no twiddles)
@@ -318,26 +367,6 @@ __device__ void fft16e(Cd (&x)[16], const Lds& L) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) L.st(pad(16 * t + c), x[c]);
     __syncthreads();
-    if constexpr (NN == 64) {
-        // pass 2: radix 4 over the four 16-point sub-transforms, twiddle W_64^{q c}:
-        // thread t forms X[c + 16 q'] for c = t + 4 s, kept in x[s + 4 q'] (point
-        // t + 4 (s + 4 q'), the natural ownership)
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            const int c = t + 4 * s4;
-            Cd v0 = L.ld(pad(c)), v1 = L.ld(pad(16 + c)), v2 = L.ld(pad(32 + c)),
-               v3 = L.ld(pad(48 + c));
-            v1 = cmul_s<SIGN>(v1, L.tab(512 + 16 + c));
-            v2 = cmul_s<SIGN>(v2, L.tab(512 + 32 + c));
-            v3 = cmul_s<SIGN>(v3, L.tab(512 + 48 + c));
-            dft4<SIGN>(v0, v1, v2, v3);
-            x[s4] = v0;
-            x[s4 + 4] = v1;
-            x[s4 + 8] = v2;
-            x[s4 + 12] = v3;
-        }
-        return;
-    }
     // pass 2: radix 16, sub-transform size 16
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = L.ld(pad(t + T * r));
@@ -353,7 +382,6 @@ __device__ void fft16e(Cd (&x)[16], const Lds& L) {
     // pass 3 (n = 1024): radix 4 over sub-transforms of size 256; twiddle
     // W_n^{r k} = W_n^{16 r (k>>4)} W_n^{r (k&15)}
     {
-        static_assert(NN == 1024 || NN == 64, "radix-16 engine: grid sizes 64 and 1024");
         Cd y[16];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -381,6 +409,8 @@ __device__ __forceinline__ void fft(Cd (&x)[Lay<NN>::P], const Lds& L, const Eng
                                     Hook&& hook) {
     if constexpr (Lay<NN>::P == 8) {
         fft8e<SIGN>(x, L, E, hook);
+    } else if constexpr (Lay<NN>::P == 4) {
+        fft4e<SIGN>(x, L, E, hook);
     } else {
         fft16e<NN, SIGN>(x, L);
         hook();
@@ -398,8 +428,8 @@ struct GpeArgs {
     const double* V0;
     const double* V1;
     double V2;
-    const dcx* tab;        // FFT twiddles (FP64): n = 4096, W_4096^m for m = 0..4095;
-                           // otherwise the 768 entries of Lds::tab
+    const dcx* tab;        // FFT twiddles (FP64): n = 4096 and 64, W_n^m for m < n;
+                           // n = 1024, the 768 entries of Lds::tab
     const dcx* Kh;         // n: e^{-i tau k^2/4} / n (FP64)
     const dcx* Kf;         // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| 0..n/2 (FP64)
     const dcx* Kfl;        // n/2 + 1: rounding residual of Kf (FP64)
@@ -473,6 +503,21 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E
         }
         __syncthreads();
         return;
+    } else if constexpr (P == 4) {
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            const dcx w0 = A.tab[(4 * r * (t & 3)) & (NN - 1)], w1 = A.tab[(r * t) & (NN - 1)];
+            E.tw[0][r - 1] = Cd{w0.re, w0.im};
+            E.tw[1][r - 1] = Cd{w1.re, w1.im};
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int m = t + T * c, mf = m <= NN / 2 ? m : NN - m;
+            const dcx k = A.Kf[mf], kl = A.Kfl[mf];
+            E.kf[c] = Cd{k.re, k.im};
+            E.kl[c] = Cx<float>{(float)kl.re, (float)kl.im};
+        }
+        return;
     } else {
         setup_tables<NN>(A, L);
     }
@@ -515,7 +560,7 @@ __device__ __forceinline__ void kick(Cd (&x)[Lay<NN>::P], const Lds& L, const En
         } else {
             const int mf = m <= NN / 2 ? m : NN - m;
             Cd k, kl;
-            if constexpr (P == 8) {
+            if constexpr (P != 16) {
                 k = E.kf[i];
                 kl = up<float>(E.kl[i]);
             } else {
@@ -959,7 +1004,7 @@ static void gpe_free(ism_problem* p) {
 
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision) {
     const size_t rs = precision == ISM_FP64 ? 16 : 8;
-    const size_t ntab = n == 4096 ? 4096 : 768;
+    const size_t ntab = n == 1024 ? 768 : n;
     return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 2 + ntab) * 16;
 }
 
@@ -1002,6 +1047,7 @@ static GpeArgs gpe_args(ism_problem* p) {
 // factors, twiddle tables and reduction slots
 static size_t gpe_shmem(int n) {
     if (n == 4096) return (2 * (size_t)kSlots8 + 504) * 16 + 16 * sizeof(double);
+    if (n == 64) return 2 * (size_t)n * 16 + 16 * sizeof(double);
     return ((size_t)n + n / 16 + (size_t)n / 2 + 1 + 768) * sizeof(dcx) +
            2 * ((size_t)n / 2 + 1) * sizeof(double) + 16 * sizeof(double);
 }
@@ -1161,9 +1207,9 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
         const long double a = 2.0L * PIL * (long double)e / (long double)m;
         return dcx{(double)cosl(a), (double)-sinl(a)};
     };
-    std::vector<dcx> tab(n == 4096 ? 4096 : 768), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
-    if (n == 4096) {                          // radix-8 engine: every root W_4096^m
-        for (int m = 0; m < 4096; ++m) tab[m] = root(m, 4096);
+    std::vector<dcx> tab(n == 1024 ? 768 : n), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
+    if (n != 1024) {                          // radix-8 and radix-4 engines: every root W_n^m
+        for (int m = 0; m < n; ++m) tab[m] = root(m, n);
     } else {
         for (int r = 0; r < 16; ++r)
             for (int k = 0; k < 16; ++k) {
