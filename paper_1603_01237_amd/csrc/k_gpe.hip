@@ -25,7 +25,7 @@
 // reads its inputs from registers and whose last pass leaves its outputs in registers in the
 // same ownership pattern, so the pointwise potential phase, the kinetic factors, the
 // trajectory and the gradient terms are formed in registers and only the exchanges between
-// passes go through LDS (split real and imaginary planes of 8-byte words).
+// passes go through LDS, as 16-byte complex slots.
 //  * n = 4096: P = 8, 512 threads (two wavefronts per SIMD), radices 8, 8, 8, 8.  The
 //    pass-3 twiddles and the kinetic factors at the owned frequencies stay in registers for
 //    the whole launch, the pass-1/2 twiddles in an LDS table; the three exchanges of a
@@ -33,11 +33,9 @@
 //    one barrier (a buffer is written again only after the barrier that follows its last
 //    reads), and each exchange has its own padding, which makes all its accesses
 //    bank-conflict free and each a per-thread base plus a compile-time offset.
-//  * n = 64: P = 4, 16 threads (one wavefront), radices 4, 4, 4; twiddles and kinetic factors
-//    in registers, the two exchanges of a transform through two LDS buffers of 16-byte slots.
-//  * n = 1024: P = 16, radices 16, 16, 4, with one in-place buffer of split real and
-//    imaginary planes padded by one element per 16 and the kinetic factors and twiddles in
-//    LDS tables.
+//  * n = 1024 and 64: P = 4, 256 and 16 threads, radix-4 passes (5 and 3); twiddles and
+//    kinetic factors in registers, the exchanges alternating between two LDS slot buffers,
+//    again one barrier and one conflict-free padding per exchange.
 // Butterflies, twiddles and the LDS state are FP64 in both precisions; the FP32 mixed path
 // stores the trajectory a_j and forms the phase e^{-i theta} in FP32.
 #include <math.h>
@@ -58,7 +56,7 @@ constexpr int kSlots8 = 4608;     // slots of an exchange buffer of the radix-8 
 
 // points per thread and threads per workgroup of the FFT engine for grid size NN
 template <int NN> struct Lay {
-    static constexpr int P = NN == 4096 ? 8 : NN == 64 ? 4 : 16;
+    static constexpr int P = NN == 4096 ? 8 : 4;
     static constexpr int T = NN / P;
 };
 
@@ -88,8 +86,6 @@ __device__ __forceinline__ Cx<R> down(Cd v) { return Cx<R>{(R)v.re, (R)v.im}; }
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 
-__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
-
 // 4-point DFT in place, roots e^{SIGN 2 pi i/4}
 template <int SIGN>
 __device__ __forceinline__ void dft4(Cd& a, Cd& b, Cd& c, Cd& d) {
@@ -101,47 +97,6 @@ __device__ __forceinline__ void dft4(Cd& a, Cd& b, Cd& c, Cd& d) {
     b = Cd{t1.re + t3.re, t1.im + t3.im};
     c = Cd{t0.re - t2.re, t0.im - t2.im};
     d = Cd{t1.re - t3.re, t1.im - t3.im};
-}
-
-// cos and sin of 2 pi m / 16, m = 0..4
-__device__ constexpr double kC16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
-                                       0.38268343236508977173, 0.0};
-
-// e^{SIGN 2 pi i m/16} for m = 0..9
-template <int SIGN>
-__device__ __forceinline__ Cd root16(int m) {
-    // reduce to the first quadrant: m = 4 q + r
-    const int q = m >> 2, r = m & 3;
-    double c = kC16[r], s = kC16[4 - r];
-    for (int k = 0; k < q; ++k) {      // multiply by i
-        const double t = c;
-        c = -s;
-        s = t;
-    }
-    return Cd{c, SIGN * s};
-}
-
-// 16-point DFT in place (x[c] <- sum_r x[r] e^{SIGN 2 pi i r c/16}) as 4 x 4.
-template <int SIGN>
-__device__ __forceinline__ void dft16(Cd (&x)[16]) {
-#pragma unroll
-    for (int r1 = 0; r1 < 4; ++r1) dft4<SIGN>(x[r1], x[r1 + 4], x[r1 + 8], x[r1 + 12]);
-#pragma unroll
-    for (int r1 = 1; r1 < 4; ++r1)
-#pragma unroll
-        for (int c2 = 1; c2 < 4; ++c2) x[r1 + 4 * c2] = cmul(x[r1 + 4 * c2], root16<SIGN>(r1 * c2));
-    Cd y[16];
-#pragma unroll
-    for (int c2 = 0; c2 < 4; ++c2) {
-        Cd p = x[4 * c2], q = x[4 * c2 + 1], r = x[4 * c2 + 2], s = x[4 * c2 + 3];
-        dft4<SIGN>(p, q, r, s);
-        y[c2] = p;
-        y[c2 + 4] = q;
-        y[c2 + 8] = r;
-        y[c2 + 12] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = y[i];
 }
 
 // 8-point DFT in place (x[c] <- sum_r x[r] e^{SIGN 2 pi i r c/8}): 4-point DFTs of the even
@@ -180,60 +135,23 @@ struct alignas(16) Cl {
 //      reads at t + 2 (t >> 4) + 576 r
 //   C: writes 512 (t >> 6) + 64c + (t & 63) at the same slot; reads at t + 512 r
 
-// LDS carve-up of a workgroup.  Complex arrays are split into real and imaginary planes of
-// doubles: the exchange accesses are then 8-byte words on consecutive (padded) addresses,
-// which the LDS serves without bank conflicts (interleaved pairs put lanes 16 bytes apart).
+// LDS carve-up of a workgroup: two exchange buffers of 16-byte slots, the radix-8 engine's
+// pass-2 twiddle table, and the slots of the workgroup reductions.
 struct Lds {
-    double* sr;        // P = 16: n + n/16, padded FFT exchange buffer, real plane;
-    double* si;        //         imaginary plane
-    Cl* x0;            // P = 8: exchange buffers (4608 slots each); P = 4: n slots each
+    Cl* x0;            // exchange buffers (radix 8: 4608 slots each; radix 4: n + n/4)
     Cl* x1;
-    Cl* tw;            // P = 8: twiddles of passes 1 and 2, [r-1][k]: W_64^{r k} at
-                       //        (r-1) 8 + k (k < 8), then W_512^{r k} at 56 + (r-1) 64 + k
-    double* kr;        // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| = 0..n/2, rounded
-    double* ki;
-    double* klr;       // n/2 + 1: its rounding residual (exact factor = kr + klr)
-    double* kli;
-    double* tr;        // 768: [0,256) W_256^{r k}; [256,512) W_n^{16 r k}; [512,768) W_n^{r k}
-    double* ti;
+    Cl* tw;            // radix 8: twiddles of pass 2, W_512^{r k} at (r-1) 64 + k
     double* red;       // 16
-    __device__ __forceinline__ Cd tab(int i) const { return Cd{tr[i], ti[i]}; }
-    __device__ __forceinline__ Cd kf(int i) const { return Cd{kr[i], ki[i]}; }
-    __device__ __forceinline__ Cd kfl(int i) const { return Cd{klr[i], kli[i]}; }
-    __device__ __forceinline__ Cd ld(int i) const { return Cd{sr[i], si[i]}; }
-    __device__ __forceinline__ void st(int i, Cd v) const {
-        sr[i] = v.re;
-        si[i] = v.im;
-    }
 };
 
 template <int NN>
 __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
+    constexpr int NS = Lay<NN>::P == 8 ? kSlots8 : NN + NN / 4;
     Lds L{};
-    if constexpr (Lay<NN>::P == 8) {
-        L.x0 = reinterpret_cast<Cl*>(raw);
-        L.x1 = L.x0 + kSlots8;
-        L.tw = L.x1 + kSlots8;
-        L.red = reinterpret_cast<double*>(L.tw + 504);
-        return L;
-    }
-    if constexpr (Lay<NN>::P == 4) {
-        L.x0 = reinterpret_cast<Cl*>(raw);
-        L.x1 = L.x0 + NN;
-        L.red = reinterpret_cast<double*>(L.x1 + NN);
-        return L;
-    }
-    constexpr int PN = NN + NN / 16;
-    L.sr = reinterpret_cast<double*>(raw);
-    L.si = L.sr + PN;
-    constexpr int KH = NN / 2 + 1;
-    L.kr = L.si + PN;
-    L.ki = L.kr + KH;
-    L.klr = L.ki + KH;
-    L.kli = L.klr + KH;
-    L.tr = L.kli + KH;
-    L.ti = L.tr + 768;
-    L.red = L.ti + 768;
+    L.x0 = reinterpret_cast<Cl*>(raw);
+    L.x1 = L.x0 + NS;
+    L.tw = L.x1 + NS;
+    L.red = reinterpret_cast<double*>(L.tw + (Lay<NN>::P == 8 ? 448 : 0));
     return L;
 }
 
@@ -242,7 +160,7 @@ __device__ __forceinline__ Lds lds_carve(unsigned char* raw) {
 //   8t + c, which pass 0 applies before its write (pass 1 reads that element as input
 //   r = w of its sub-transform position c); uniform over the wavefront (scalar registers);
 //   tw[r-1] = W_4096^{r t}, the twiddles of pass 3 (r = 1..7; pass 2 reads its twiddles
-//   from an LDS table);
+//   W_512^{r (t mod 64)} from an LDS table);
 //   kf[c] + kl[c] = e^{-i tau k^2/2} / n at the owned frequency t + 512 c (rounded value and
 //   its rounding residual, the residual kept in FP32).
 struct Eng8 {
@@ -251,18 +169,18 @@ struct Eng8 {
     Cd kf[8];
     Cx<float> kl[8];
 };
-// Constants of the radix-4 engine (n = 64, thread t < 16): tw[0][r-1] = W_16^{r (t mod 4)},
-// tw[1][r-1] = W_64^{r t} (passes 1 and 2, r = 1..3); kf, kl as for the radix-8 engine at
-// the owned frequencies t + 16 c.
+// Constants of the radix-4 engine (n = 4^NP, T = n/4 threads, thread t): tw[p-1][r-1] =
+// W_{4S}^{r (t mod S)}, S = 4^p, the twiddles of pass p = 1..NP-1 (r = 1..3); kf, kl as
+// for the radix-8 engine at the owned frequencies t + T c.
+template <int NP>
 struct Eng4 {
-    Cd tw[2][3];
+    Cd tw[NP - 1][3];
     Cd kf[4];
     Cx<float> kl[4];
 };
-struct Eng16 {};
+template <int NN> struct Log4 { static constexpr int v = NN == 64 ? 3 : NN == 1024 ? 5 : 0; };
 template <int NN>
-using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8,
-                               std::conditional_t<Lay<NN>::P == 4, Eng4, Eng16>>;
+using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8, Eng4<Log4<NN>::v>>;
 
 // Radix-8 Stockham pass p = 1, 2, 3 over sub-transforms of size S = 8^p: thread t reads
 // x_r = A[t + 512 r] (exchange A, B or C), multiplies by W_{8S}^{r (t mod S)} (pass 1: done
@@ -283,7 +201,7 @@ __device__ __forceinline__ void pass8(Cd (&x)[8], const Cl* a, Cl* b, const Lds&
 #pragma unroll
         for (int r = 1; r < 8; ++r) {
             Cl w;
-            if constexpr (PASS == 2) w = L.tw[56 + (r - 1) * 64 + (t & 63)];
+            if constexpr (PASS == 2) w = L.tw[(r - 1) * 64 + (t & 63)];
             else w = Cl{E.tw[r - 1].re, E.tw[r - 1].im};
             x[r] = cmul_s<SIGN>(x[r], Cd{w.re, w.im});
         }
@@ -324,81 +242,60 @@ __device__ __forceinline__ void fft8e(Cd (&x)[8], const Lds& L, const Eng8& E, H
     pass8<SIGN, 3>(x, u, nullptr, L, E);         // C -> registers
 }
 
-// radix-4 engine (n = 64, one wavefront of 16 threads): pass p = 0, 1, 2 over sub-transforms
-// of size S = 4^p; thread t reads x_r = A[t + 16 r] (pass 0: its registers), multiplies by
-// W_{4S}^{r (t mod S)} and forms the 4-point DFT; passes 0 and 1 write y_c to
-// B[4S (t / S) + S c + (t mod S)], pass 2 keeps X[t + 16 c] = y_c.  Pass 0 writes buffer 0
-// and pass 1 buffer 1: the next transform's writes come after a barrier that follows every
-// read of the buffer they overwrite.
-template <int SIGN, typename Hook>
-__device__ __forceinline__ void fft4e(Cd (&x)[4], const Lds& L, const Eng4& E, Hook&& hook) {
+// Radix-4 engine (n = 4^NP, T = n/4 threads): pass p = 0..NP-1 over sub-transforms of size
+// S = 4^p; thread t reads x_r = A[t + T r] (pass 0: its registers), multiplies by
+// W_{4S}^{r (t mod S)} and forms the 4-point DFT; passes p < NP-1 write y_c to
+// B[4S (t / S) + S c + (t mod S)] (exchange p, buffer p mod 2), the last pass keeps
+// X[t + T c] = y_c.  Slot of element i in exchange p: i + (i >> 4) (p = 0), i + 4 (i >> 4)
+// (p = 1), i (p >= 2): every access is a per-thread base plus a compile-time offset, and
+// the 16 lanes served together by the LDS hit distinct slots modulo 16 in every pattern.
+// A transform has an even number of exchanges (2 or 4), so each restarts on buffer 0, and
+// a buffer is written again only after the barrier that follows its last reads.
+template <int NN, int SIGN, int PASS>
+__device__ __forceinline__ void pass4(Cd (&x)[4], const Lds& L, const Eng<NN>& E) {
+    constexpr int T = NN / 4, NP = Log4<NN>::v, S = 1 << (2 * PASS);
     const int t = threadIdx.x;
-    dft4<SIGN>(x[0], x[1], x[2], x[3]);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) L.x0[4 * t + c] = Cl{x[c].re, x[c].im};
-    lds_sync();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const Cl v = L.x0[t + 16 * r];
-        x[r] = r ? cmul_s<SIGN>(Cd{v.re, v.im}, E.tw[0][r - 1]) : Cd{v.re, v.im};
-    }
-    dft4<SIGN>(x[0], x[1], x[2], x[3]);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) L.x1[16 * (t >> 2) + 4 * c + (t & 3)] = Cl{x[c].re, x[c].im};
-    lds_sync();
-    hook();
+    const Cl* a = (PASS - 1) % 2 ? L.x1 : L.x0;
+    // reads of exchange PASS-1: slot(t + T r) = base + r (T + pad per T elements)
+    const Cl* pa = a + (PASS == 1 ? t + (t >> 4) : PASS == 2 ? t + 4 * (t >> 4) : t);
+    constexpr int RS = PASS == 1 ? T + T / 16 : PASS == 2 ? T + T / 4 : T;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const Cl v = L.x1[t + 16 * r];
-        x[r] = r ? cmul_s<SIGN>(Cd{v.re, v.im}, E.tw[1][r - 1]) : Cd{v.re, v.im};
+        const Cl v = pa[RS * r];
+        x[r] = r ? cmul_s<SIGN>(Cd{v.re, v.im}, E.tw[PASS - 1][r - 1]) : Cd{v.re, v.im};
     }
     dft4<SIGN>(x[0], x[1], x[2], x[3]);
+    if constexpr (PASS < NP - 1) {
+        Cl* b = PASS % 2 ? L.x1 : L.x0;
+        // writes of exchange PASS: element 4S (t / S) + S c + (t mod S)
+        Cl* pb = b + (PASS == 1 ? 20 * (t >> 2) + (t & 3) : 4 * S * (t / S) + (t & (S - 1)));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pb[S * c] = Cl{x[c].re, x[c].im};
+    }
 }
 
-// radix-16 engine (n = 1024)
-template <int NN, int SIGN>
-__device__ void fft16e(Cd (&x)[16], const Lds& L) {
-    static_assert(NN == 1024, "radix-16 engine: n = 1024");
-    constexpr int T = NN / 16;
+template <int NN, int SIGN, typename Hook>
+__device__ __forceinline__ void fft4e(Cd (&x)[4], const Lds& L, const Eng<NN>& E, Hook&& hook) {
+    constexpr int NP = Log4<NN>::v;
+    static_assert(NP == 3 || NP == 5, "radix-4 engine: n = 64 or 1024");
     const int t = threadIdx.x;
-    // pass 1: radix 16, sub-transform size 1 (no twiddles)
-    dft16<SIGN>(x);
-    __syncthreads();                          // earlier readers of the buffer are done
+    dft4<SIGN>(x[0], x[1], x[2], x[3]);          // pass 0
+    Cl* pu = L.x0 + 4 * t + (t >> 2);            // slot(4t + c) = 4t + (t >> 2) + c
 #pragma unroll
-    for (int c = 0; c < 16; ++c) L.st(pad(16 * t + c), x[c]);
-    __syncthreads();
-    // pass 2: radix 16, sub-transform size 16
-#pragma unroll
-    for (int r = 0; r < 16; ++r) x[r] = L.ld(pad(t + T * r));
-    const int k = t & 15;
-#pragma unroll
-    for (int r = 1; r < 16; ++r) x[r] = cmul_s<SIGN>(x[r], L.tab(r * 16 + k));
-    dft16<SIGN>(x);
-    __syncthreads();                          // every thread has read its inputs
-    const int base = (t >> 4) * 256 + k;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) L.st(pad(base + 16 * c), x[c]);
-    __syncthreads();
-    // pass 3 (n = 1024): radix 4 over sub-transforms of size 256; twiddle
-    // W_n^{r k} = W_n^{16 r (k>>4)} W_n^{r (k&15)}
-    {
-        Cd y[16];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int j = t + 64 * s, kh = j >> 4, kl = j & 15;
-            Cd v0 = L.ld(pad(j)), v1 = L.ld(pad(j + 256)), v2 = L.ld(pad(j + 512)),
-               v3 = L.ld(pad(j + 768));
-            v1 = cmul_s<SIGN>(v1, cmul(L.tab(256 + 16 + kh), L.tab(512 + 16 + kl)));
-            v2 = cmul_s<SIGN>(v2, cmul(L.tab(256 + 32 + kh), L.tab(512 + 32 + kl)));
-            v3 = cmul_s<SIGN>(v3, cmul(L.tab(256 + 48 + kh), L.tab(512 + 48 + kl)));
-            dft4<SIGN>(v0, v1, v2, v3);
-            y[s] = v0;
-            y[s + 4] = v1;
-            y[s + 8] = v2;
-            y[s + 12] = v3;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = y[i];
+    for (int c = 0; c < 4; ++c) pu[c] = Cl{x[c].re, x[c].im};
+    lds_sync();
+    pass4<NN, SIGN, 1>(x, L, E);
+    lds_sync();
+    if constexpr (NP == 5) {
+        pass4<NN, SIGN, 2>(x, L, E);
+        lds_sync();
+        pass4<NN, SIGN, 3>(x, L, E);
+        lds_sync();
+        hook();
+        pass4<NN, SIGN, 4>(x, L, E);
+    } else {
+        hook();
+        pass4<NN, SIGN, 2>(x, L, E);
     }
 }
 
@@ -407,14 +304,10 @@ __device__ void fft16e(Cd (&x)[16], const Lds& L) {
 template <int NN, int SIGN, typename Hook>
 __device__ __forceinline__ void fft(Cd (&x)[Lay<NN>::P], const Lds& L, const Eng<NN>& E,
                                     Hook&& hook) {
-    if constexpr (Lay<NN>::P == 8) {
+    if constexpr (Lay<NN>::P == 8)
         fft8e<SIGN>(x, L, E, hook);
-    } else if constexpr (Lay<NN>::P == 4) {
-        fft4e<SIGN>(x, L, E, hook);
-    } else {
-        fft16e<NN, SIGN>(x, L);
-        hook();
-    }
+    else
+        fft4e<NN, SIGN>(x, L, E, hook);
 }
 
 struct NoHook {
@@ -428,8 +321,7 @@ struct GpeArgs {
     const double* V0;
     const double* V1;
     double V2;
-    const dcx* tab;        // FFT twiddles (FP64): n = 4096 and 64, W_n^m for m < n;
-                           // n = 1024, the 768 entries of Lds::tab
+    const dcx* tab;        // FFT twiddles W_n^m, m < n (FP64)
     const dcx* Kh;         // n: e^{-i tau k^2/4} / n (FP64)
     const dcx* Kf;         // n/2 + 1: e^{-i tau k^2/2} / n at |frequency| 0..n/2 (FP64)
     const dcx* Kfl;        // n/2 + 1: rounding residual of Kf (FP64)
@@ -450,25 +342,7 @@ struct GpeArgs {
     int update;
 };
 
-// kinetic factors and twiddles of the radix-16 engine into LDS
-template <int NN>
-__device__ __forceinline__ void setup_tables(const GpeArgs& A, const Lds& L) {
-    constexpr int T = NN / 16;
-    const int t = threadIdx.x;
-    for (int i = t; i <= NN / 2; i += T) {
-        L.kr[i] = A.Kf[i].re;
-        L.ki[i] = A.Kf[i].im;
-        L.klr[i] = A.Kfl[i].re;
-        L.kli[i] = A.Kfl[i].im;
-    }
-    for (int i = t; i < 768; i += T) {
-        L.tr[i] = A.tab[i].re;
-        L.ti[i] = A.tab[i].im;
-    }
-    __syncthreads();
-}
-
-// engine constants into registers (P = 8) or tables into LDS (P = 16); potentials into
+// engine constants into registers (the radix-8 pass-2 twiddles into LDS); potentials into
 // registers
 template <int NN>
 __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E,
@@ -481,9 +355,9 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E
         v1[i] = A.V1[t + T * i];
     }
     if constexpr (P == 8) {
-        // W_64^{r k} = W_4096^{64 r k}, W_512^{r k} = W_4096^{8 r k}
-        for (int i = t; i < 504; i += T) {
-            const int m = i < 56 ? 64 * (i / 8 + 1) * (i & 7) : 8 * ((i - 56) / 64 + 1) * ((i - 56) & 63);
+        // W_512^{r k} = W_4096^{8 r k}
+        for (int i = t; i < 448; i += T) {
+            const int m = 8 * (i / 64 + 1) * (i & 63);
             L.tw[i] = Cl{A.tab[m].re, A.tab[m].im};
         }
         const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -503,12 +377,16 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E
         }
         __syncthreads();
         return;
-    } else if constexpr (P == 4) {
+    } else {
+        constexpr int NP = Log4<NN>::v;
 #pragma unroll
-        for (int r = 1; r < 4; ++r) {
-            const dcx w0 = A.tab[(4 * r * (t & 3)) & (NN - 1)], w1 = A.tab[(r * t) & (NN - 1)];
-            E.tw[0][r - 1] = Cd{w0.re, w0.im};
-            E.tw[1][r - 1] = Cd{w1.re, w1.im};
+        for (int q = 1; q < NP; ++q) {            // W_{4S}^{m} = W_n^{(n / 4S) m}, S = 4^q
+            const int S = 1 << (2 * q);
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const dcx w = A.tab[((NN / (4 * S)) * r * (t & (S - 1))) & (NN - 1)];
+                E.tw[q - 1][r - 1] = Cd{w.re, w.im};
+            }
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -517,9 +395,6 @@ __device__ __forceinline__ void setup(const GpeArgs& A, const Lds& L, Eng<NN>& E
             E.kf[c] = Cd{k.re, k.im};
             E.kl[c] = Cx<float>{(float)kl.re, (float)kl.im};
         }
-        return;
-    } else {
-        setup_tables<NN>(A, L);
     }
 }
 
@@ -540,12 +415,11 @@ __device__ __forceinline__ double block_sum(double v, const Lds& L) {
     return s;
 }
 
-// x <- F^-1 diag(k) F x, k at the owned frequencies: the fused kinetic factor from LDS
-// (kt == nullptr) or a table in global memory; CONJ uses conj(k) (adjoint kicks).  The fused
-// factor is applied as its rounded value plus the rounding residual: a rounded factor alone
-// makes the same relative error at every one of the K steps of a sweep, which adds up
-// coherently (about 5e-13 over 10^4 steps).  The factor depends on |frequency| only, so the
-// LDS holds the frequencies 0..n/2.
+// x <- F^-1 diag(k) F x, k at the owned frequencies: the fused kinetic factor held in
+// registers (kt == nullptr) or a table in global memory; CONJ uses conj(k) (adjoint kicks).
+// The fused factor is applied as its rounded value plus the rounding residual: a rounded
+// factor alone makes the same relative error at every one of the K steps of a sweep, which
+// adds up coherently (about 5e-13 over 10^4 steps).
 template <int NN, bool CONJ, typename Hook>
 __device__ __forceinline__ void kick(Cd (&x)[Lay<NN>::P], const Lds& L, const Eng<NN>& E,
                                      const Cd* kt, Hook&& hook) {
@@ -558,15 +432,7 @@ __device__ __forceinline__ void kick(Cd (&x)[Lay<NN>::P], const Lds& L, const En
             const Cd k = kt[m];
             x[i] = CONJ ? cmulc(x[i], k) : cmul(x[i], k);
         } else {
-            const int mf = m <= NN / 2 ? m : NN - m;
-            Cd k, kl;
-            if constexpr (P != 16) {
-                k = E.kf[i];
-                kl = up<float>(E.kl[i]);
-            } else {
-                k = L.kf(mf);
-                kl = L.kfl(mf);
-            }
+            const Cd k = E.kf[i], kl = up<float>(E.kl[i]);
             const Cd lo = CONJ ? cmulc(x[i], kl) : cmul(x[i], kl);
             const Cd v = x[i];
             if (CONJ)
@@ -1004,8 +870,7 @@ static void gpe_free(ism_problem* p) {
 
 size_t gpe_footprint_extra(size_t n, int K, int N, int batch, int precision) {
     const size_t rs = precision == ISM_FP64 ? 16 : 8;
-    const size_t ntab = n == 1024 ? 768 : n;
-    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (2 * n + 2 + ntab) * 16;
+    return (size_t)batch * K * n * rs + 2 * (size_t)batch * (N + 1) * n * 16 + (3 * n + 2) * 16;
 }
 
 size_t gpe_frozen_bytes(size_t n, int N, int batch) {
@@ -1042,14 +907,11 @@ static GpeArgs gpe_args(ism_problem* p) {
     return A;
 }
 
-// FP64 in both precisions.  n = 4096: two exchange buffers and the reduction slots (the
-// engine's constants are in registers); otherwise the padded exchange buffer, kinetic
-// factors, twiddle tables and reduction slots
+// two exchange buffers of 16-byte slots, the radix-8 engine's pass-2 twiddle table and the
+// reduction slots (FP64 in both precisions)
 static size_t gpe_shmem(int n) {
-    if (n == 4096) return (2 * (size_t)kSlots8 + 504) * 16 + 16 * sizeof(double);
-    if (n == 64) return 2 * (size_t)n * 16 + 16 * sizeof(double);
-    return ((size_t)n + n / 16 + (size_t)n / 2 + 1 + 768) * sizeof(dcx) +
-           2 * ((size_t)n / 2 + 1) * sizeof(double) + 16 * sizeof(double);
+    if (n == 4096) return (2 * (size_t)kSlots8 + 448) * 16 + 16 * sizeof(double);
+    return 2 * ((size_t)n + n / 4) * 16 + 16 * sizeof(double);
 }
 
 template <int NN, typename R>
@@ -1207,17 +1069,8 @@ int gpe_create(ism_problem* p, int n, double L, double g, const double* V0, cons
         const long double a = 2.0L * PIL * (long double)e / (long double)m;
         return dcx{(double)cosl(a), (double)-sinl(a)};
     };
-    std::vector<dcx> tab(n == 1024 ? 768 : n), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
-    if (n != 1024) {                          // radix-8 and radix-4 engines: every root W_n^m
-        for (int m = 0; m < n; ++m) tab[m] = root(m, n);
-    } else {
-        for (int r = 0; r < 16; ++r)
-            for (int k = 0; k < 16; ++k) {
-                tab[r * 16 + k] = root((long long)r * k, 256);          // pass 2
-                tab[256 + r * 16 + k] = root(16LL * r * k, n);          // pass 3, high part
-                tab[512 + r * 16 + k] = root((long long)r * k, n);      // pass 3, low part
-            }
-    }
+    std::vector<dcx> tab(n), kh(n), kf(n / 2 + 1), kfl(n / 2 + 1);
+    for (int m = 0; m < n; ++m) tab[m] = root(m, n);          // every root W_n^m
     // wavenumbers k_f = 2 pi f / (n dx) in FP64, formed as (2 pi) (f (1 / (n dx))) with
     // dx = L / n (the grid's frequencies in the usual fftfreq order); the kinetic phase
     // -tau k^2 / 4 and its exponential are then evaluated in extended precision
