@@ -61,7 +61,8 @@ typedef enum ism_precision {
     ISM_FP64 = 0,           /* plain path: every step in FP64 */
     ISM_FP32_MIXED = 1      /* FP32 complex propagation with FP32 accumulate; per-step
                                generator data and all overlaps, gradients, boundary states,
-                               J and F formed in FP64 */
+                               J and F formed in FP64 (small state problems on the one-launch
+                               solve compute in FP64 throughout; see launch_per_pass) */
 } ism_precision;
 
 typedef enum ism_kind {
@@ -109,12 +110,14 @@ typedef struct ism_options {
                                creating and destroying the handle never synchronises the whole
                                device (default 0: hipMalloc / hipFree) */
     int step_map;           /* ism_step_map of a state problem (default ISM_STEP_EXP) */
-    int launch_per_pass;    /* 0 (default): small FP64 state problems (d <= 4, at most 4
-                               controls and 64 slices, exponential map) run ism_iterate and
-                               their served iterations as one persistent launch, one workgroup
-                               per instance holding every phase of Algorithm 1; 1: always the
-                               sequence of per-pass launches.  Both give the iterates of
-                               Algorithm 1 to FP64 rounding (not bitwise the same). */
+    int launch_per_pass;    /* 0 (default): small state problems (d <= 4, at most 4 controls
+                               and 64 slices, exponential map) run ism_iterate and their served
+                               iterations as one persistent launch, one workgroup per instance
+                               holding every phase of Algorithm 1, in FP64 for both precisions
+                               (the solve is bound by the serial chains of its slices, so an
+                               FP32 mixed handle gains nothing from FP32 there); 1: always the
+                               sequence of per-pass launches.  In FP64 both give the iterates
+                               of Algorithm 1 to FP64 rounding (not bitwise the same). */
     int gpe_frozen;         /* condensate (ism_problem_create_gpe, n_grid 64 or 1024): 1 builds
                                the boundaries of every iteration after the first by
                                propagator assembling with the density frozen at the last

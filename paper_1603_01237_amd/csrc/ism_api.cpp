@@ -394,8 +394,9 @@ static int sp_create(ism_problem* p, const double* H0, int h0_batched, const dou
     const size_t msz = (size_t)B * p->N * d * d * 2 *
                        (p->precision == ISM_FP64 ? sizeof(double) : sizeof(float));
     if ((st = dev_alloc(p, &p->M, msz))) return st;
-    if (p->precision == ISM_FP64 && !p->step_cn && d <= kSmallD && C <= kSmallC &&
-        p->N <= kSmallN) {
+    // small state problems take the one-launch solve in both precisions: it computes in
+    // FP64, and its time is set by the serial chains of the slices, not by arithmetic
+    if (!p->step_cn && d <= kSmallD && C <= kSmallC && p->N <= kSmallN) {
         if ((st = small_setup(p, H0, h0_batched, Hc))) return st;
         p->small = true;
     }
@@ -896,7 +897,8 @@ size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kin
     bytes += 3 * B * (N + 1) * dd * 16;              // Psi, Lam, phi
     bytes += B * N * dd * dd * 2 * rs;               // slice propagators
     bytes += (size_t)(n_ctrl + 1) * dd * 8 * 24 + B * 64;   // generators, params
-    if (precision == ISM_FP64)                       // one-launch solve of small problems
+    // one-launch solve of small problems (either precision)
+    if (small_workspace_bytes(d, n_ctrl, K, N, batch))
         bytes += small_workspace_bytes(d, n_ctrl, K, N, batch) + B * 32 +
                  (size_t)batch * (n_ctrl + 1) * kSmallD * kSmallD * 16;
     return bytes;

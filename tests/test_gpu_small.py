@@ -1,5 +1,6 @@
-"""GPU parity of the one-launch solve of small FP64 state problems (d <= 4, at most 4
-controls and 64 slices): every iteration of Algorithm 1 for an instance in one workgroup.
+"""GPU parity of the one-launch solve of small state problems (d <= 4, at most 4 controls
+and 64 slices): every iteration of Algorithm 1 for an instance in one workgroup, in FP64
+for handles of either precision.
 
 It replaces the per-pass launch sequence in ism_iterate and in served iterations; both are
 FP64 evaluations of the same iterates, so they are compared with each other and with the
@@ -113,6 +114,29 @@ def test_one_launch_runs_as_one_launch():
         h.iterate(50, p.rho)
         kt = h.kernel_times()
     assert set(kt) == {"small_solve"} and kt["small_solve"][0] == 1, kt
+
+
+def test_fp32_handle_takes_the_fp64_one_launch_solve():
+    """An FP32 mixed handle of a small problem iterates through the same FP64 one-launch
+    solve as the FP64 handle (same inputs, same kernel: bitwise the same J history and
+    controls); with launch_per_pass its FP32 per-pass loop stays within the FP32 bar."""
+    from paper_1603_01237_amd import _lib
+    _say("case small fp32 handle")
+    p = problems.spin2()
+    res = {}
+    for prec, lpp in (("fp64", False), ("fp32", False), ("fp32", True)):
+        with _lib.from_problem(p, precision=prec, launch_per_pass=lpp) as h:
+            h.set_timing(True)
+            Jh, done = h.iterate(20, p.rho)
+            kt = h.kernel_times()
+            res[(prec, lpp)] = (Jh[:, 0].copy(), done, h.get_controls()[0].copy(), set(kt))
+    J64, d64, u64, k64 = res[("fp64", False)]
+    J32, d32, u32, k32 = res[("fp32", False)]
+    Jp, dp, up, kp = res[("fp32", True)]
+    assert k64 == k32 == {"small_solve"} and "small_solve" not in kp
+    assert d32 == d64 and np.array_equal(J32, J64) and np.array_equal(u32, u64)
+    assert dp == d64 and np.max(np.abs(Jp - J64)) <= 1e-4
+    assert _rel(up, u64) <= 1e-4
 
 
 def test_one_launch_batch_with_freezing():
