@@ -992,6 +992,7 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 // coefficient and its rounding residual delta_r is put back once per sub-step as the phase
 // e^{-i delta_r} (delta_r ~ 1e-9, so the commutator it leaves out is ~1e-10 per step).
 constexpr int RPL = 3;
+constexpr bool kTriDpp64 = true;       // FP64 lane edges by DPP shifts (tri_edges)
 
 // Per-lane coefficients of the tridiagonal layout: rows r0 .. r0+RPL-1 of instance b,
 // scaled by tau_sub; dg the (rounded) diagonal, dl its FP32 rounding residual, Lc / Rc the
@@ -1039,13 +1040,41 @@ __device__ __forceinline__ void tri_coeffs(const SpArgs& a, int b, int r0, bool 
 
 // Neighbour rows across the lane edges: the row below this lane's first row and the row
 // above its last row.
+// FP64: the neighbours are lanes lane - 1 and lane + 1 (lane 0 and lane 63 their own), so
+// the values move by whole-wavefront DPP shifts (wave_shr:1, wave_shl:1), VALU moves
+// without the LDS round trip of ds_bpermute; the FP64 Horner chain waits on these fetches
+// at every term, with half the wavefronts per SIMD of the FP32 kernels to hide them.
+// FP32 keeps ds_bpermute: those kernels are bound by VALU issue, which the moves would add to.
+__device__ __forceinline__ int dpp_shift(int v, bool prev) {
+    return prev ? __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false)     // wave_shr:1
+                : __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false);    // wave_shl:1
+}
+__device__ __forceinline__ double lane_shift(double v, bool prev) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    const int lo = dpp_shift((int)(unsigned)(bits & 0xffffffffull), prev);
+    const int hi = dpp_shift((int)(unsigned)(bits >> 32), prev);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned long long)(unsigned)lo));
+}
+
+__device__ __forceinline__ float lane_shift(float v, bool prev) {
+    return __int_as_float(dpp_shift(__float_as_int(v), prev));
+}
+
 template <typename R>
 __device__ __forceinline__ void tri_edges(const R (&xr)[RPL], const R (&xi)[RPL], int left,
                                           int right, R& lr, R& li, R& rr, R& ri) {
-    lr = lane_fetch(left, xr[RPL - 1]);
-    li = lane_fetch(left, xi[RPL - 1]);
-    rr = lane_fetch(right, xr[0]);
-    ri = lane_fetch(right, xi[0]);
+    if constexpr (sizeof(R) == 8 && kTriDpp64) {
+        lr = lane_shift(xr[RPL - 1], true);
+        li = lane_shift(xi[RPL - 1], true);
+        rr = lane_shift(xr[0], false);
+        ri = lane_shift(xi[0], false);
+    } else {
+        lr = lane_fetch(left, xr[RPL - 1]);
+        li = lane_fetch(left, xi[RPL - 1]);
+        rr = lane_fetch(right, xr[0]);
+        ri = lane_fetch(right, xi[0]);
+    }
 }
 
 // h = (D + L shift_down + R shift_up) x on this lane's rows
