@@ -28,7 +28,8 @@
 // passes go through LDS, as 16-byte complex slots.
 //  * n = 4096: P = 8, 512 threads (two wavefronts per SIMD), radices 8, 8, 8, 8.  The
 //    pass-3 twiddles and the kinetic factors at the owned frequencies stay in registers for
-//    the whole launch, the pass-1/2 twiddles in an LDS table; the three exchanges of a
+//    the whole launch, the pass-2 twiddles in an LDS table, and the pass-1 twiddles, uniform
+//    over a wavefront, are applied by pass 0 from scalar registers; the three exchanges of a
 //    transform alternate between two LDS buffers of 16-byte complex slots, so each needs
 //    one barrier (a buffer is written again only after the barrier that follows its last
 //    reads), and each exchange has its own padding, which makes all its accesses
