@@ -185,8 +185,8 @@ using Eng = std::conditional_t<Lay<NN>::P == 8, Eng8, Eng4<Log4<NN>::v>>;
 
 // Radix-8 Stockham pass p = 1, 2, 3 over sub-transforms of size S = 8^p: thread t reads
 // x_r = A[t + 512 r] (exchange A, B or C), multiplies by W_{8S}^{r (t mod S)} (pass 1: done
-// by pass 0 before its write) and forms the 8-point DFT; passes 1 and 2 write y_c to B[8S (t / S) + S c + (t mod S)] (exchange B or C),
-// pass 3 keeps X[t + 512 c] = y_c.
+// by pass 0 before its write) and forms the 8-point DFT; passes 1 and 2 write y_c to
+// B[8S (t / S) + S c + (t mod S)] (exchange B or C), pass 3 keeps X[t + 512 c] = y_c.
 template <int SIGN, int PASS>
 __device__ __forceinline__ void pass8(Cd (&x)[8], const Cl* a, Cl* b, const Lds& L,
                                       const Eng8& E) {
