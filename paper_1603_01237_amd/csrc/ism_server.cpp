@@ -76,9 +76,17 @@ size_t state_len(const ism_request& q) {
 }
 
 // may b join a group headed by a?  Both finite state problems (the batched sparse path), equal
-// in everything but the diagonal of H0
+// in everything but the diagonal of H0; or both condensate problems (one workgroup per
+// instance in every kernel of that path), equal in everything but the initial controls
 bool mergeable(const Req* a, const Req* b) {
     const ism_request &x = a->r, &y = b->r;
+    if (x.model == ISM_REQ_GPE && y.model == ISM_REQ_GPE) {
+        if (x.precision != y.precision || x.n_grid != y.n_grid || x.L != y.L || x.g != y.g ||
+            x.V2 != y.V2 || x.K != y.K || x.N != y.N || x.T != y.T || x.rho != y.rho ||
+            x.fid_stop != y.fid_stop || x.max_iter != y.max_iter)
+            return false;
+        return a->V0 == b->V0 && a->V1 == b->V1 && a->psi0 == b->psi0 && a->target == b->target;
+    }
     if (x.model != ISM_REQ_FINITE || y.model != ISM_REQ_FINITE) return false;
     if (x.kind != ISM_STATE || y.kind != ISM_STATE) return false;
     if (x.precision != y.precision || x.d != y.d || x.n_ctrl != y.n_ctrl || x.K != y.K ||
@@ -438,9 +446,12 @@ static std::vector<Req*> admission_group(ism_server* s) {
         if (mergeable(head, s->queue[i])) g.push_back(s->queue[i]);
     while (!g.empty()) {
         const ism_request& q = head->r;
-        const size_t est = g.size() == 1 ? head->est
-                                         : ism_problem_footprint(q.d, q.n_ctrl, q.K, q.N, (int)g.size(),
-                                                                 q.kind, q.precision, 0);
+        const bool gpe = q.model == ISM_REQ_GPE;
+        const size_t est = g.size() == 1
+                               ? head->est
+                               : ism_problem_footprint(gpe ? 1 : q.d, gpe ? 1 : q.n_ctrl, q.K, q.N,
+                                                       (int)g.size(), gpe ? ISM_STATE : q.kind,
+                                                       q.precision, gpe ? q.n_grid : 0);
         if (est != 0 && s->in_use + est <= s->budget) break;
         g.pop_back();
     }

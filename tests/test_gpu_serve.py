@@ -196,3 +196,35 @@ def test_merged_requests_equal_their_lone_runs():
         if len(rot) <= k < len(rot) + len(spins):
             iters_spins.add(rm["iters"])
     assert len(iters_spins) > 1           # the merged spins froze at different iterations
+
+
+def test_merged_condensate_requests_equal_their_lone_runs():
+    """Condensate requests on one grid, potential, time grid and stopping rule that differ
+    only in their initial controls share one batched handle (one workgroup per instance in
+    every kernel of the path): each returns bitwise what it returns alone and what
+    ism_iterate returns on its own handle.  A request with another slice count runs apart."""
+    from paper_1603_01237_amd import _lib
+    same = [(problems.gpe(seed=70 + i, n=64, L=20.0, g=1.0, dt=8.0 / 256, K=256, N=8,
+                          x_target=1.0), 0.1, 5, 2.0, "fp64") for i in range(3)]
+    other = [(problems.gpe(seed=80, n=64, L=20.0, g=1.0, dt=8.0 / 256, K=256, N=4,
+                           x_target=1.0), 0.1, 5, 2.0, "fp64")]
+    items = same + other
+    _say("case serve merge condensate", len(items))
+    res, st = _serve(items, ipr=2)
+    assert st["completed"] == len(items) and st["failed"] == 0
+    assert st["merged"] == len(same) - 1, st
+    assert st["groups"] == 2, st
+    for k, it in enumerate(items):
+        alone, _ = _serve([it], ipr=2)
+        rm, um = res[k]
+        ra, ua = alone[0]
+        assert rm["state"] == _lib.REQ_DONE and ra["state"] == _lib.REQ_DONE
+        assert rm["iters"] == ra["iters"] == it[2], (k, rm, ra)
+        assert np.array_equal(um, ua), k
+        assert rm["F"] == ra["F"] and rm["J"] == ra["J"], k
+        p, rho, mi, fs, pr = it
+        with _lib.from_problem(p, precision=pr) as h:
+            _, done = h.iterate(mi, rho, fid_stop=fs)
+            assert done == rm["iters"]
+            assert np.array_equal(h.get_controls()[0, :, 0], np.ravel(um)), k
+
