@@ -338,10 +338,12 @@ size_t ism_problem_footprint(int d, int n_ctrl, int K, int N, int batch, int kin
  * admitted in arrival order while the device memory they would hold
  * (ism_problem_footprint, or the handle's actual bytes if larger) fits in hbm_budget.
  * The head of the queue is admitted together with every queued request that differs from
- * it only in the diagonal of H0 (finite state problems with the same d, controls, psi0,
- * target, off-diagonal H0, T, K, N, precision, rho, fid_stop and max_iter; at most 256):
- * they run as the instances of one batched handle, so one set of launches serves them all,
- * and each instance freezes on its own.  Each such group has its own handle and HIP stream,
+ * it only in the diagonal of H0 and the initial controls (finite state problems with the
+ * same d, controls, psi0, target, off-diagonal H0, T, K, N, precision, rho, fid_stop and
+ * max_iter), or, for a condensate request, only in the initial controls (same n_grid, L,
+ * g, V0, V1, V2, psi0, target, T, K, N, precision, rho, fid_stop and max_iter); at most
+ * 256: they run as the instances of one batched handle, so one set of launches serves them
+ * all, and each instance freezes on its own.  Each such group has its own handle and HIP stream,
  * so the kernels of different groups overlap on the device.  Work is issued in chunks of
  * iters_per_round iterations with no host synchronisation; ism_server_progress polls the
  * chunks' events, finishes requests (copying their controls out), retires finished groups
