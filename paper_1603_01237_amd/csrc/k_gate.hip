@@ -49,6 +49,9 @@ constexpr int WMAX_G = 16;    // largest union-pattern width
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// complex LDS slot of the gradient's Krylov buffers (real and imaginary part side by side)
+template <typename R> struct alignas(2 * sizeof(R)) Cx { R re, im; };
+
 template <typename R> struct Acc;
 template <> struct Acc<float> { typedef f4 T; };
 template <> struct Acc<double> { typedef d4 T; };
@@ -953,8 +956,29 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateG
         hcol[w] = cc;
     }
     for (int q = 0; q < gg.C; ++q) gacc[q * VS + t] = 0.0;     // own slots only
-    // Krylov buffer `buf` (0/1) of column slot `c`, plane 0 (re) or 1 (im)
-    auto vbp = [&](int c, int buf, int plane) { return vb + ((c * 2 + buf) * 2 + plane) * VS; };
+    // Krylov buffer `buf` (0/1) of column slot `c`, 2 VS reals.  FP32 keeps (re, im) of a
+    // slot side by side, so that a gather is one 8-byte LDS read; FP64 keeps two planes
+    // (16-byte reads at the gathered slots run slower than two 8-byte ones).
+    constexpr bool kIl = sizeof(R) == 4;
+    auto vbp = [&](int c, int buf) { return vb + (c * 2 + buf) * 2 * VS; };
+    auto ld = [&](const R* p, int i) {
+        if constexpr (kIl) return reinterpret_cast<const Cx<R>*>(p)[i];
+        else return Cx<R>{p[i], p[VS + i]};
+    };
+    auto st = [&](R* p, int i, R re, R im) {
+        if constexpr (kIl) {
+            reinterpret_cast<Cx<R>*>(p)[i] = Cx<R>{re, im};
+        } else {
+            p[i] = re;
+            p[VS + i] = im;
+        }
+    };
+    // S_w of this row, summed over every column the thread works on (only the sum enters
+    // the gradient, and a dead column adds exact zeros); contracted with the controls once,
+    // after the last column
+    R swr[WT], swi[WT];
+#pragma unroll
+    for (int w = 0; w < WT; ++w) swr[w] = swi[w] = 0;
     for (int kk = 0; kk < CBW; kk += ngrp * NC) {
         if (cb * CBW + kk >= d) break;        // uniform over the workgroup
         // columns k_c of X_j (x) and Y_j (y) for this thread's group, c < NC
@@ -982,8 +1006,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateG
         __syncthreads();                      // the previous columns' readers of vb are done
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            vbp(c, 0, 0)[t] = yr[c];
-            vbp(c, 0, 1)[t] = yi[c];
+            st(vbp(c, 0), t, yr[c], yi[c]);
         }
 #pragma unroll
         for (int a = 0; a <= MK; ++a) {
@@ -992,19 +1015,18 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateG
                     __syncthreads();          // p_{a-1} is in buffer (a-1) & 1
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        const R* ysr = vbp(c, (a - 1) & 1, 0) + base;
-                        const R* ysi = vbp(c, (a - 1) & 1, 1) + base;
+                        const R* ys = vbp(c, (a - 1) & 1);
                         R nyr = 0, nyi = 0;
 #pragma unroll
                         for (int w = 0; w < WT; ++w) {
                             const int cc = hcol[w];
-                            const R vr = ysr[cc], vi = ysi[cc];
+                            const Cx<R> v = ld(ys, base + cc);
+                            const R vr = v.re, vi = v.im;
                             nyr = fma(hvr[w], vr, fma(-hvi[w], vi, nyr));
                             nyi = fma(hvr[w], vi, fma(hvi[w], vr, nyi));
                         }
                         if (a < m) {          // p_m is read by nobody
-                            vbp(c, a & 1, 0)[t] = nyr;
-                            vbp(c, a & 1, 1)[t] = nyi;
+                            st(vbp(c, a & 1), t, nyr, nyi);
                         }
                         yr[c] = nyr;
                         yi[c] = nyi;
@@ -1028,16 +1050,10 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateG
             }
         }
         // phase 2: r_b = (tau H')^b x; S_w += conj(t_b) r_b(col_w)
-        R swr[NC][WT], swi[NC][WT];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int w = 0; w < WT; ++w) swr[c][w] = swi[c][w] = 0;
         __syncthreads();                      // phase 1's readers of vb are done
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            vbp(c, 0, 0)[t] = xr[c];
-            vbp(c, 0, 1)[t] = xi[c];
+            st(vbp(c, 0), t, xr[c], xi[c]);
         }
 #pragma unroll
         for (int b = 0; b <= MK; ++b) {
@@ -1045,44 +1061,36 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateG
                 __syncthreads();              // r_b is in buffer b & 1
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    const R* xsr = vbp(c, b & 1, 0) + base;
-                    const R* xsi = vbp(c, b & 1, 1) + base;
+                    const R* xs = vbp(c, b & 1);
                     const R cr = ttr[c][b], ci = tti[c][b];
                     R nxr = 0, nxi = 0;
 #pragma unroll
                     for (int w = 0; w < WT; ++w) {
                         const int cc = hcol[w];
-                        const R ur = xsr[cc], ui = xsi[cc];
-                        swr[c][w] = fma(cr, ur, fma(ci, ui, swr[c][w]));
-                        swi[c][w] = fma(cr, ui, fma(-ci, ur, swi[c][w]));
+                        const Cx<R> v = ld(xs, base + cc);
+                        const R ur = v.re, ui = v.im;
+                        swr[w] = fma(cr, ur, fma(ci, ui, swr[w]));
+                        swi[w] = fma(cr, ui, fma(-ci, ur, swi[w]));
                         nxr = fma(hvr[w], ur, fma(-hvi[w], ui, nxr));
                         nxi = fma(hvr[w], ui, fma(hvi[w], ur, nxi));
                     }
                     if (b < m) {
-                        vbp(c, (b + 1) & 1, 0)[t] = nxr;
-                        vbp(c, (b + 1) & 1, 1)[t] = nxi;
+                        st(vbp(c, (b + 1) & 1), t, nxr, nxi);
                     }
                 }
             }
         }
-        // per control: Im(h S_w) summed over the control's entries of this row, in FP64
+    }
+    // per control: Im(h S_w) summed over the control's entries of this row, in FP64
 #pragma unroll
-        for (int w = 0; w < WT; ++w) {
-            if (w < gg.W && r < d) {
-                double sr = 0.0, si = 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    if (live[c]) {
-                        sr += (double)swr[c][w];
-                        si += (double)swi[c][w];
-                    }
-                }
-                const size_t e0 = ((size_t)r * gg.W + w) * gg.CW;
-                for (int e = 0; e < gg.CW; ++e) {
-                    const int q = gg.wq[e0 + e];
-                    const dcx hv = gg.wv[e0 + e];
-                    gacc[q * VS + t] += hv.re * si + hv.im * sr;
-                }
+    for (int w = 0; w < WT; ++w) {
+        if (w < gg.W && r < d) {
+            const double sr = swr[w], si = swi[w];
+            const size_t e0 = ((size_t)r * gg.W + w) * gg.CW;
+            for (int e = 0; e < gg.CW; ++e) {
+                const int q = gg.wq[e0 + e];
+                const dcx hv = gg.wv[e0 + e];
+                gacc[q * VS + t] += hv.re * si + hv.im * sr;
             }
         }
     }
@@ -1186,6 +1194,11 @@ __global__ __launch_bounds__(256) void k_gate_grad_cn(GateGen gg, const R* XY, l
             }
         }
     };
+    // S_w = sum over the thread's columns of conj(A y)_r (A x)_{col_w}, in FP64, contracted
+    // with the controls once after the last column
+    double swr[WT], swi[WT];
+#pragma unroll
+    for (int w = 0; w < WT; ++w) swr[w] = swi[w] = 0.0;
     for (int kk = 0; kk < CBW; kk += ngrp) {
         if (cb * CBW + kk >= d) break;        // uniform over the workgroup
         const int k = cb * CBW + kk + grp;
@@ -1209,16 +1222,21 @@ __global__ __launch_bounds__(256) void k_gate_grad_cn(GateGen gg, const R* XY, l
                 if (w < gg.W) {
                     const int cc = hcol[w];
                     const R ur = ax[cc], ui = ax[VS + cc];
-                    // S_w = conj(A y)_r (A x)_{col_w}
-                    const double sr = (double)ayr * ur + (double)ayi * ui;
-                    const double si = (double)ayr * ui - (double)ayi * ur;
-                    const size_t e0 = ((size_t)r * gg.W + w) * gg.CW;
-                    for (int e = 0; e < gg.CW; ++e) {
-                        const int q = gg.wq[e0 + e];
-                        const dcx hv = gg.wv[e0 + e];
-                        gacc[q * VS + t] += hv.re * si + hv.im * sr;
-                    }
+                    swr[w] += (double)ayr * ur + (double)ayi * ui;
+                    swi[w] += (double)ayr * ui - (double)ayi * ur;
                 }
+            }
+        }
+    }
+    // per control: Im(h S_w) summed over the control's entries of this row
+#pragma unroll
+    for (int w = 0; w < WT; ++w) {
+        if (w < gg.W && r < d) {
+            const size_t e0 = ((size_t)r * gg.W + w) * gg.CW;
+            for (int e = 0; e < gg.CW; ++e) {
+                const int q = gg.wq[e0 + e];
+                const dcx hv = gg.wv[e0 + e];
+                gacc[q * VS + t] += hv.re * swi[w] + hv.im * swr[w];
             }
         }
     }
