@@ -171,6 +171,7 @@ def gate_grad_flops(prob, prec):
       16 m w_r        the Krylov sequences p_a = (tau H')^a y and r_b = (tau H')^b x
       2 (m+1)(m+2)    the weights t_b = sum_a conj(w_ab) p_a (real weight times complex)
       8 (m+1) w_r     S_w = sum_b conj(t_b) r_b(col_w)
+and once per step and row, S_w being summed over the columns first:
       4 nnz_c(r)      Im(h S_w) per control entry of the row (summed over controls)."""
     import numpy as np
     K, d, C = prob.K, prob.d, prob.C
@@ -197,7 +198,7 @@ def gate_grad_flops(prob, prec):
         while m < cap and rem > tol:
             m += 1
             rem = rem * x / (m + 2)
-        total += d * (16 * m * w_sum + d * 2 * (m + 1) * (m + 2) + 8 * (m + 1) * w_sum + 4 * nnz_c)
+        total += d * (16 * m * w_sum + d * 2 * (m + 1) * (m + 2) + 8 * (m + 1) * w_sum) + 4 * nnz_c
     return total
 
 

@@ -42,7 +42,7 @@ namespace {
 constexpr int GT = 64;        // output tile (rows and columns)
 constexpr int MMAX_G = 24;    // largest Taylor / Krylov order
 constexpr int RB = 8;         // rows of U built per workgroup
-constexpr int CBW = 32;       // columns per workgroup in the gradient kernel
+constexpr int CBW = 128;      // columns per workgroup in the gradient kernel
 constexpr int CMAX_G = 32;    // largest number of controls in the gate path
 constexpr int WMAX_G = 16;    // largest union-pattern width
 
