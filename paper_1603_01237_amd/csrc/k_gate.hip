@@ -292,7 +292,8 @@ __global__ __launch_bounds__(256) void k_gate_build(GateGen gg, R* U, long long 
         lpc = 1;
         while (lpc < d) lpc <<= 1;
     }
-    const int c = t & (lpc - 1), base = t - c, grp = t / lpc, ngrp = dp / lpc;
+    // lpc is dp (a multiple of 64, not always a power of two) or a power of two up to 32
+    const int c = t % lpc, base = t - c, grp = t / lpc, ngrp = dp / lpc;
     const double* uj = gg.u + (size_t)j * gg.C;
     // row c of conj(H_j - s) on the union pattern
     dcx hv[WT];
@@ -925,7 +926,8 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateG
         lpc = 1;
         while (lpc < d) lpc <<= 1;
     }
-    const int r = t & (lpc - 1), base = t - r, grp = t / lpc, ngrp = dp / lpc;
+    // lpc is dp (a multiple of 64, not always a power of two) or a power of two up to 32
+    const int r = t % lpc, base = t - r, grp = t / lpc, ngrp = dp / lpc;
     const double* uj = gg.u + (size_t)j * gg.C;
     int m;
     {
@@ -1131,7 +1133,8 @@ __global__ __launch_bounds__(256) void k_gate_grad_cn(GateGen gg, const R* XY, l
         lpc = 1;
         while (lpc < d) lpc <<= 1;
     }
-    const int r = t & (lpc - 1), base = t - r, grp = t / lpc, ngrp = dp / lpc;
+    // lpc is dp (a multiple of 64, not always a power of two) or a power of two up to 32
+    const int r = t % lpc, base = t - r, grp = t / lpc, ngrp = dp / lpc;
     const double* uj = gg.u + (size_t)j * gg.C;
     int nt;
     {

@@ -248,6 +248,27 @@ def spin_chain_gate(seed: int = 1002, n: int = 8, T: float = 20.0, K: int = 2000
                          T, K, N, u0, np.zeros(K), rho, iters, kind="gate", meta={"J": J})
 
 
+def banded_gate(seed: int = 1006, d: int = 160, K: int = 6, N: int = 2,
+                T: float = 0.06) -> FiniteProblem:
+    """Gate synthesis with a dimension that is no power of two: H0 Hermitian with a random
+    diagonal U(-1, 1) and nearest-neighbour couplings U(0.5, 1.5) e^{i phi}; control 0 a real
+    symmetric coupling of i and i+1 (weights U(0.5, 1)), control 1 an imaginary antisymmetric
+    coupling of i and i+3; identity towards a Haar-random W; u0 ~ U(-0.5, 0.5)."""
+    rng = np.random.default_rng(seed)
+    H0 = np.diag(rng.uniform(-1, 1, d)).astype(np.complex128)
+    cpl = rng.uniform(0.5, 1.5, d - 1) * np.exp(1j * rng.uniform(0, 2 * np.pi, d - 1))
+    H0 += np.diag(cpl, 1) + np.diag(cpl.conj(), -1)
+    w0 = rng.uniform(0.5, 1.0, d - 1)
+    w1 = rng.uniform(0.5, 1.0, d - 3)
+    Hc = np.zeros((2, d, d), dtype=np.complex128)
+    Hc[0] = np.diag(w0, 1) + np.diag(w0, -1)
+    Hc[1] = 1j * (np.diag(w1, 3) - np.diag(w1, -3))
+    W = haar_unitary(d, rng)
+    u0 = rng.uniform(-0.5, 0.5, size=(1, K, 2))
+    return FiniteProblem("banded_gate", H0, Hc, np.eye(d, dtype=np.complex128), W, T, K, N, u0,
+                         np.zeros(K), 0.5, 5, kind="gate")
+
+
 def spin_chain_state(seed: int, n: int, T: float, K: int, N: int, iters: int = 200,
                      rho: float = 0.5) -> FiniteProblem:
     """Chain state transfer |0..0> -> |1..1> (same Hamiltonian family as the gate problem)."""

@@ -55,6 +55,8 @@ CASES = [
     # 16 or more slices: the FP64 boundaries run as a chunked scan (ragged chunks at N = 19)
     ("chain4_gate_K57_N19_bscan", lambda: _gate_problem(4, 57, 19)),
     ("spin2_gate_K40_N20_bscan", lambda: _spin2_gate(40, 20, T=2.0)),
+    # d = 160: two column blocks of the gradient, the second one partly filled
+    ("banded_gate_d160_K6_N2", lambda: problems.banded_gate(d=160, K=6, N=2)),
 ]
 
 
