@@ -55,8 +55,11 @@ CASES = [
     # 16 or more slices: the FP64 boundaries run as a chunked scan (ragged chunks at N = 19)
     ("chain4_gate_K57_N19_bscan", lambda: _gate_problem(4, 57, 19)),
     ("spin2_gate_K40_N20_bscan", lambda: _spin2_gate(40, 20, T=2.0)),
-    # d = 160: two column blocks of the gradient, the second one partly filled
+    # d = 160: padded to 192 rows, two column blocks of the gradient (the second partly
+    # filled); d = 100: padded to 128; d = 24: groups of 32 lanes with dead rows in each
     ("banded_gate_d160_K6_N2", lambda: problems.banded_gate(d=160, K=6, N=2)),
+    ("banded_gate_d100_K9_N3", lambda: problems.banded_gate(seed=7, d=100, K=9, N=3, T=0.09)),
+    ("banded_gate_d24_K20_N4", lambda: problems.banded_gate(seed=8, d=24, K=20, N=4, T=0.2)),
 ]
 
 
