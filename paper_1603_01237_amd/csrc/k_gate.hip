@@ -905,9 +905,12 @@ __device__ constexpr WabTable kWab = make_wab();
 // Two bounds MK are launched: the one with MK = mks runs when every step's order is at
 // most mks (kmax, from the step build at the same controls; then the order of every step is
 // the same as with the larger bound, and so is the result), the other one otherwise.  The
-// smaller bound holds fewer registers and more wavefronts per SIMD.
+// smaller bound holds fewer registers.  Two wavefronts per SIMD, except FP64 at d <= 64:
+// at d = 256 three FP64 wavefronts (168 registers) spilled and took 18.0 ms against 12.5;
+// at d = 32, whose workgroups are one wavefront, the third wavefront hides more latency
+// than its spill costs (1.91 against 2.06 ms for the five-spin density gradient).
 template <typename R, int MK, int WT, int VS, int NC>
-__global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 3) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
+__global__ __launch_bounds__(256, sizeof(R) == 8 && VS == 64 ? 3 : 2) void k_gate_grad(GateGen gg, const R* XY, long long xy_plane,
                                                    double* gpart, int ncb, int* flags,
                                                    const int* kmax, int mks) {
     if ((*kmax <= mks) != (MK == mks)) return;      // the other bound's launch does this work
