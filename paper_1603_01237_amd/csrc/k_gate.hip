@@ -95,12 +95,32 @@ template <typename R, int KC>
 __global__ __launch_bounds__(256, sizeof(R) == 4 ? 4 : 2) void k_zgemm(GemmArgs g) {
     __shared__ R As[2][KC][GT + 1];   // [re/im][k][i]
     __shared__ R Bs[2][KC][GT + 1];   // [re/im][k][j]
-    const GemmEntry e = g.e[blockIdx.y];
+    // XCD-aware placement.  Workgroups go to the 8 XCDs round-robin by linear id, so in the
+    // plain (tile, entry) order the tiles of one product land on every XCD and each XCD's
+    // L2 fetches both of its operands.  Here linear id L of the first nt * ne8 workgroups
+    // (ne8: the entry count rounded down to a multiple of 8) runs tile (L / 8) % nt of entry
+    // ((L / 8) / nt) * 8 + L % 8: every tile of an entry on one XCD.  The remaining entries
+    // keep the plain order.  Both parts are bijections, so each tile is computed as before.
+    int tile, ent;
+    {
+        const int nt = gridDim.x, ne8 = gridDim.y & ~7;
+        const int L = blockIdx.y * nt + blockIdx.x;
+        if (L < nt * ne8) {
+            const int s = L >> 3;
+            ent = (s / nt) * 8 + (L & 7);
+            tile = s % nt;
+        } else {
+            const int q = L - nt * ne8;
+            ent = ne8 + q / nt;
+            tile = q % nt;
+        }
+    }
+    const GemmEntry e = g.e[ent];
     const R* A = reinterpret_cast<const R*>(g.A) + e.a;
     const R* Bm = reinterpret_cast<const R*>(g.B) + e.b;
     R* Cm = reinterpret_cast<R*>(g.C) + e.c;
     const int tilesN = g.N / GT;
-    const int i0 = (blockIdx.x / tilesN) * GT, j0 = (blockIdx.x % tilesN) * GT;
+    const int i0 = (tile / tilesN) * GT, j0 = (tile % tilesN) * GT;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const bool hA = e.flags & 1, hB = e.flags & 2, addB = e.flags & 4;
